@@ -1,0 +1,157 @@
+/*
+ * hz.h -- C ABI of the MI355X (gfx950) solver for the tetrahedral-stencil
+ * FFT homogenization method of A. Finel, "A fast and robust discrete
+ * FFT-based solver for computational homogenization" (arXiv 2405.11168).
+ *
+ * The library iterates the displacement-based basic scheme of the paper's
+ * Algorithm 1 (Sec. 2.6) on a periodic N1 x N2 x N3 voxel grid:
+ *
+ *   1. eps^T1(q) = D(q) (x)_s u(q),  eps^T2(q) = -conj(D(q)) (x)_s u(q)   (eq. deps_dep_Q)
+ *   2. inverse FFT of the twelve strain components                          (eq. IFT_1)
+ *   3. sigma^Tk(r) = lambda(r) : (Ebar + eps^Tk(r))                          (eq. linear_elasticity_Kk)
+ *   4. forward FFT                                                          (eq. FT)
+ *   5. u(q) <- u(q) - Omega(q).{sigma^T1(q).conj(D(q)) - sigma^T2(q).D(q)}   (eq. basic_scheme_dep_2)
+ *
+ * with D of eq. Dq, Omega of eq. Green_tensor (set to 0 at q = 0 and q = (pi,pi,pi)),
+ * and the convergence measure eps = L2/||<sigma>|| of eqs. L2-norm and tolerance.
+ * Every step runs in hand-written HIP kernels on device-resident fields.
+ *
+ * Conventions
+ *   - Grid sizes: every N_i even and >= 2 (Sec. 2.1), prime factors in {2,3,5,7};
+ *     N1 <= 4096, N2, N3 <= 2048.
+ *   - Phase map: uint16 [n3][n2][n1], x fastest.
+ *   - Stiffness: engineering-shear Voigt 6x6, row-major, order (11,22,33,23,13,12):
+ *     sigma_I = C_IJ gamma_J with gamma = (e11,e22,e33,2e23,2e13,2e12).
+ *   - Macroscopic strains E and mean stresses: tensor components (11,22,33,23,13,12).
+ *   - Voxel size d = 1 (results do not depend on it).
+ *
+ * Ownership
+ *   - The caller owns every host array; the library copies what it needs.
+ *   - All device memory the solver touches is one caller-owned workspace
+ *     (hz_workspace_bytes / hz_bind_workspace); the library never allocates
+ *     device memory.  Work is issued on the caller's HIP stream.
+ *   - A handle is used by one host thread at a time; handles are independent.
+ *
+ * Errors: every int-returning call returns HZ_OK (0) or one of the codes
+ * below; no C++ exception crosses the ABI and hz_last_error() gives a
+ * thread-local message for the last failing call.
+ */
+#ifndef HZ_H
+#define HZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HZ_OK 0
+#define HZ_NOT_CONVERGED 1   /* max_iters reached; outputs written from the last iterate  */
+#define HZ_STAGNATED 2       /* refinement stopped gaining above tol (rounding floor)      */
+#define HZ_EINVAL (-1)       /* NULL pointer, size <= 0, unsupported size or option        */
+#define HZ_EODD (-2)         /* a grid dimension is odd (the scheme needs even N_i)        */
+#define HZ_ENOMATERIAL (-3)  /* hz_set_material not called                                */
+#define HZ_ENOTSPD (-4)      /* a stiffness is not positive semi-definite, or the
+                                reference medium is not positive definite                */
+#define HZ_EWORKSPACE (-5)   /* workspace not bound or too small                           */
+#define HZ_EHIP (-6)         /* a HIP runtime call failed                                  */
+#define HZ_EDIVERGED (-7)    /* residual became NaN/Inf or grew by 1e3 (reference medium
+                                too soft)                                                  */
+
+typedef struct hz_grid_s* hz_grid;
+
+/* Arithmetic of the iteration.  HZ_FP64: every kernel in FP64.
+ * HZ_FP32_REFINE: fields and FFTs in FP32 on a correction, anchored by FP64
+ * sweeps of the full pipeline; the stop decision is always an FP64 residual. */
+#define HZ_FP64 0
+#define HZ_FP32_REFINE 1
+
+typedef struct {
+  double tol;               /* stop at the first iterate k with eps_k < tol (eq. tolerance)   */
+  int32_t max_iters;        /* cap on updates (FP64) or on FP32 inner updates (refinement)     */
+  int32_t precision;        /* HZ_FP64 or HZ_FP32_REFINE                                        */
+  int32_t ref_mode;         /* 0: automatic reference medium; 1: use ref_C                      */
+  double ref_C[36];         /* reference medium lambda0, Voigt 6x6, when ref_mode = 1           */
+  int32_t fixed_iters;      /* >= 0: run exactly this many updates, ignore tol (parity tests)   */
+  int32_t check_every;      /* host looks at the device stop flags every this many iterations  */
+  double* trace_residual;   /* optional [n_loads][max_iters+1]: eps_k of every iterate (FP64)   */
+  double* trace_mean;       /* optional [n_loads][max_iters+1][6]: <sigma>_k                    */
+  double inner_rho;         /* refinement: inner loop stops at rho * eps of its FP64 sweep      */
+  int32_t inner_max;        /* refinement: cap on inner iterations per outer round              */
+} hz_opts;
+
+typedef struct {
+  int32_t status;           /* HZ_OK, HZ_NOT_CONVERGED, HZ_STAGNATED or HZ_EDIVERGED           */
+  int32_t iters;            /* updates applied to the reported iterate                          */
+  int32_t outer_rounds;     /* FP64 sweeps (refinement); 0 for HZ_FP64                          */
+  int32_t precision_used;   /* HZ_FP64 or HZ_FP32_REFINE                                        */
+  double residual;          /* eps of the reported iterate, measured in FP64                    */
+  double seconds;           /* device time from solve start to the reported iterate            */
+  double seconds_to_1e6;    /* device time to the first FP64-verified eps < 1e-6, or -1         */
+} hz_info;
+
+/* Fill *o with defaults: tol 1e-8, max_iters 2000, HZ_FP64, automatic reference,
+ * fixed_iters -1, check_every 8, no traces, inner_rho 1e-3, inner_max 400. */
+void hz_default_opts(hz_opts* o);
+
+/* Create a grid handle for an n1 x n2 x n3 periodic cell (Sec. 2.1).
+ * Returns HZ_EODD for an odd size, HZ_EINVAL for other unsupported sizes. */
+int hz_create_grid(int32_t n1, int32_t n2, int32_t n3, hz_grid* out);
+
+/* Set the microstructure: n_phases stiffness matrices C_voigt[n_phases][6][6]
+ * and the phase id of every voxel phase[n3][n2][n1] (< n_phases).  Zero
+ * stiffness (voids) is allowed.  Host arrays are copied; device copies are made
+ * by hz_bind_workspace. */
+int hz_set_material(hz_grid g, int32_t n_phases, const double* C_voigt, const uint16_t* phase);
+
+/* Bytes of device workspace needed to solve up to n_loads load cases at once
+ * in the given precision; negative error code on invalid arguments. */
+int64_t hz_workspace_bytes(hz_grid g, int32_t precision, int32_t n_loads);
+
+/* Bind a caller-owned device buffer (>= hz_workspace_bytes(g, precision, n_loads),
+ * 256-byte aligned) and the HIP stream (hipStream_t, may be NULL) all work is issued
+ * on, and upload the material and tables into it.  Must follow hz_set_material;
+ * call again after changing the material. */
+int hz_bind_workspace(hz_grid g, void* dev_ptr, int64_t bytes, void* hip_stream,
+                      int32_t precision, int32_t n_loads);
+
+/* Solve n_loads strain-controlled problems with applied mean strains E[n_loads][6]
+ * (Sec. 2.3: the mean strain equals the applied strain).
+ * Outputs (each may be NULL):
+ *   sigma_mean[n_loads][6]  <sigma> of the reported iterate (FP64)
+ *   eps_out, sig_out        host [n_loads][6][n3][n2][n1] FP64 fields of eq. final_fields
+ *   info[n_loads]
+ * Returns the worst per-load status (negative codes first). */
+int hz_solve(hz_grid g, int32_t n_loads, const double* E, const hz_opts* o,
+             double* sigma_mean, double* eps_out, double* sig_out, hz_info* info);
+
+/* Effective stiffness: the six unit load cases (gamma_J = 1) solved as one batch;
+ * column J of C_eff (row-major 6x6 Voigt) is <sigma> of case J.  Needs a workspace
+ * bound for n_loads >= 6. */
+int hz_effective_stiffness(hz_grid g, const hz_opts* o, double C_eff[36], hz_info info[6]);
+
+/* Copy the displacement spectrum of load `load` after the last solve to host:
+ * out[3][n1/2+1][n3][n2] complex (interleaved re,im) FP64, in the library's phase
+ * convention u~(q) = exp(i q.(1/2,1/2,1/2)) u(q) (u(q) of eq. FT_u). */
+int hz_get_displacement(hz_grid g, int32_t load, double* out);
+
+/* Reference medium the automatic rule picks for a set of phases: isotropic with
+ * nu0 = 0 and Mandel modulus at the midpoint of the smallest and largest Mandel
+ * eigenvalue over all phases (pure host function). */
+int hz_reference_medium(int32_t n_phases, const double* C_voigt, double C0_out[36]);
+
+/* Per-kernel device timing with HIP events on the bound stream.
+ * hz_profile(g, 1) starts recording (and clears totals), hz_profile(g, 0) stops.
+ * hz_profile_read fills up to max entries: name (static string), total ms, launches;
+ * returns the number of kernel kinds. */
+int hz_profile(hz_grid g, int32_t enable);
+int hz_profile_read(hz_grid g, int32_t max, const char** names, double* total_ms, int64_t* launches);
+
+void hz_destroy_grid(hz_grid g);
+const char* hz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HZ_H */

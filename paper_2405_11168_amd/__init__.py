@@ -1,0 +1,180 @@
+"""MI355X (gfx950) solver for the tetrahedral-stencil FFT homogenization method
+(Finel, arXiv 2405.11168): the displacement-based basic scheme of Algorithm 1
+iterated entirely in hand-written HIP kernels behind the C ABI of include/hz.h.
+
+PyTorch provides device memory (the caller-owned workspace) and the HIP
+stream; every step of the iteration runs in libhz.so.  There is no CPU path:
+without the built library the solver raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _abi
+from ._abi import (HZ_EDIVERGED, HZ_FP32_REFINE, HZ_FP64, HZ_NOT_CONVERGED, HZ_OK, HZ_STAGNATED, HzError,
+                   check, hz_info, hz_opts)
+
+__all__ = ["Grid", "SolveResult", "HZ_FP64", "HZ_FP32_REFINE", "HzError", "reference_medium", "lib"]
+
+
+def lib():
+    return _abi.load()
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def reference_medium(C):
+    """Reference medium of the library's automatic rule for phases C[P,6,6] (host only)."""
+    C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1, 6, 6)
+    out = np.zeros(36)
+    check(lib().hz_reference_medium(len(C), _dptr(C), _dptr(out)))
+    return out.reshape(6, 6)
+
+
+@dataclass
+class SolveResult:
+    mean_sigma: np.ndarray          # [n_loads, 6] tensor comps
+    status: np.ndarray              # [n_loads]
+    iters: np.ndarray
+    outer_rounds: np.ndarray
+    residual: np.ndarray
+    seconds: np.ndarray
+    seconds_to_1e6: np.ndarray
+    rc: int
+    trace_residual: np.ndarray | None = None   # [n_loads, T]
+    trace_mean: np.ndarray | None = None       # [n_loads, T, 6]
+    eps: np.ndarray | None = None              # [n_loads, 6, N3, N2, N1]
+    sigma: np.ndarray | None = None
+
+
+class Grid:
+    """One periodic N1 x N2 x N3 cell (hz_grid handle) with a torch-owned workspace."""
+
+    def __init__(self, n1: int, n2: int, n3: int):
+        L = lib()
+        h = ctypes.c_void_p()
+        check(L.hz_create_grid(n1, n2, n3, ctypes.byref(h)))
+        self._h = h
+        self.shape = (n1, n2, n3)
+        self._ws = None
+        self._bound = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().hz_destroy_grid(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # -- material ---------------------------------------------------------------
+    def set_material(self, C, phase):
+        """C: [P,6,6] Voigt stiffness; phase: [N3,N2,N1] ids (uint16)."""
+        C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1, 6, 6)
+        phase = np.ascontiguousarray(phase, dtype=np.uint16)
+        n1, n2, n3 = self.shape
+        if phase.shape != (n3, n2, n1):
+            raise ValueError(f"phase map must be [N3,N2,N1] = {(n3, n2, n1)}, got {phase.shape}")
+        check(lib().hz_set_material(self._h, len(C), _dptr(C),
+                                    phase.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))))
+        self._bound = None
+
+    # -- workspace -------------------------------------------------------------
+    def workspace_bytes(self, precision=HZ_FP64, n_loads=1) -> int:
+        return check(lib().hz_workspace_bytes(self._h, precision, n_loads))
+
+    def bind(self, precision=HZ_FP64, n_loads=1, device="cuda", stream=None):
+        """Allocate the device workspace with torch and hand it to the library."""
+        import torch
+
+        nbytes = self.workspace_bytes(precision, n_loads)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        s = stream if stream is not None else torch.cuda.current_stream(self._ws.device)
+        self._stream = s
+        check(lib().hz_bind_workspace(self._h, ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+                                      ctypes.c_void_p(s.cuda_stream), precision, n_loads))
+        self._bound = (precision, n_loads)
+
+    def _ensure(self, precision, n_loads):
+        b = self._bound
+        if b is None or b[0] != precision or b[1] < n_loads:
+            self.bind(precision, n_loads)
+
+    # -- solve -----------------------------------------------------------------
+    def solve(self, E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1,
+              fields=False, trace=False, check_every=8, inner_rho=1e-3, inner_max=400) -> SolveResult:
+        E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
+        nl = E.shape[0]
+        self._ensure(precision, nl)
+        o = hz_opts()
+        lib().hz_default_opts(ctypes.byref(o))
+        o.tol = tol
+        o.max_iters = max_iters
+        o.precision = precision
+        o.fixed_iters = fixed_iters
+        o.check_every = check_every
+        o.inner_rho = inner_rho
+        o.inner_max = inner_max
+        if C0 is not None:
+            o.ref_mode = 1
+            o.ref_C[:] = np.asarray(C0, dtype=np.float64).reshape(36).tolist()
+        T = (fixed_iters if fixed_iters >= 0 else max_iters) + 1
+        tr = tm = None
+        if trace:
+            tr = np.full((nl, T), np.nan)
+            tm = np.full((nl, T, 6), np.nan)
+            o.trace_residual = _dptr(tr)
+            o.trace_mean = _dptr(tm)
+        sm = np.zeros((nl, 6))
+        infos = (hz_info * nl)()
+        n1, n2, n3 = self.shape
+        eps = sig = None
+        if fields:
+            eps = np.zeros((nl, 6, n3, n2, n1))
+            sig = np.zeros((nl, 6, n3, n2, n1))
+        rc = check(lib().hz_solve(self._h, nl, _dptr(E), ctypes.byref(o), _dptr(sm),
+                                  _dptr(eps) if fields else None, _dptr(sig) if fields else None, infos))
+        return SolveResult(
+            mean_sigma=sm,
+            status=np.array([i.status for i in infos]),
+            iters=np.array([i.iters for i in infos]),
+            outer_rounds=np.array([i.outer_rounds for i in infos]),
+            residual=np.array([i.residual for i in infos]),
+            seconds=np.array([i.seconds for i in infos]),
+            seconds_to_1e6=np.array([i.seconds_to_1e6 for i in infos]),
+            rc=rc, trace_residual=tr, trace_mean=tm, eps=eps, sigma=sig)
+
+    def effective_stiffness(self, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, **kw):
+        """C_eff (6x6 Voigt): column J = <sigma> of unit load gamma_J = 1, six loads in one batch."""
+        E = np.zeros((6, 6))
+        for J in range(6):
+            E[J, J] = 1.0 if J < 3 else 0.5
+        r = self.solve(E, tol=tol, max_iters=max_iters, precision=precision, C0=C0, **kw)
+        return r.mean_sigma.T.copy(), r
+
+    def displacement(self, load=0):
+        """u~(q) of the reported iterate: complex [3, N1/2+1, N3, N2] (library phase convention)."""
+        n1, n2, n3 = self.shape
+        out = np.zeros((3, n1 // 2 + 1, n3, n2, 2))
+        check(lib().hz_get_displacement(self._h, load, _dptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    # -- profiling ---------------------------------------------------------------
+    def profile(self, enable=True):
+        check(lib().hz_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        n = 64
+        names = (ctypes.c_char_p * n)()
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        k = check(lib().hz_profile_read(self._h, n, names, ms, cnt))
+        return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(k, n)) if cnt[i] > 0}

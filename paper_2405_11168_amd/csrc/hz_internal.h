@@ -1,0 +1,98 @@
+// Internal structures shared by the HIP kernels and the host driver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hz {
+
+constexpr int kThreads = 256;   // work-group size of every kernel (4 wave64)
+constexpr int kMaxPasses = 16;
+
+// Factorisation of a transform length into Stockham radix passes.
+struct Plan {
+  int L;
+  int np;
+  int radix[kMaxPasses];
+};
+
+// Spectral storage is [comp][h1][h3][h2] with h1 in [0, N1/2] outermost, so the
+// y and z transforms read unit-stride rows and no tile is ragged in h1.
+struct Geo {
+  int N1, N2, N3;
+  int H1;          // N1/2 + 1
+  long long S;     // H1 * N3 * N2 : complex elements per component
+  long long N;     // N1 * N2 * N3
+};
+
+// Per-problem descriptor.  One launch serves many same-shape problems (load
+// cases of one grid, or requests of a serving group); blockIdx.y picks one.
+struct Desc {
+  void* spec;            // 12 strain/stress spectra, kernel precision
+  void* u[2];            // displacement spectra (3 comps), ping-pong, kernel precision
+  void* u64;             // refinement: FP64 anchor U (3 comps)
+  void* r32;             // refinement: FP64-sweep residual stored in FP32 (3 comps)
+  const uint16_t* phase; // [N3][N2][N1]
+  const double* C64;     // [n_phases][36] Voigt
+  const float* C32;      // [n_phases][36] Voigt
+  double* part_sig;      // [nbx][6] FP64 partial sums of (sigma^T1 + sigma^T2)/2
+  double* part_res;      // [nbq] FP64 partial sums of w |r/2|^2
+  double* status;        // [16] device-side state, see St below
+  double* eps_out;       // optional real-space output fields [6][N] FP64
+  double* sig_out;
+  double* trace;         // optional [max_iters+1][7]: eps_k, <sigma>_k
+  double Ebar[6];        // applied mean strain (tensor comps); zero for a correction
+  double C0[81];         // reference medium, full 3x3x3x3 tensor
+  double tol;
+  int max_iters;
+  int fixed_iters;
+  int trace_len;
+  int pad;
+};
+
+// Layout of Desc::status (doubles; integers stored exactly)
+enum St {
+  ST_DONE = 0,       // 1 once the stop rule fired (kernels of later iterations skip)
+  ST_ITERS = 1,      // iterate index k at which it stopped
+  ST_PARITY = 2,     // u[] slot holding u_k
+  ST_ERR = 3,        // eps_k of the last measured iterate
+  ST_MEAN = 4,       // 4..9 <sigma>_k
+  ST_L2SQ = 10,      // sum w |r/2|^2
+  ST_K = 11,         // iterations measured so far
+  ST_FIRST_ERR = 12, // eps_0 (divergence watchdog)
+  ST_NORM = 13,      // ||<sigma>|| used for the criterion
+  ST_REF = 14,       // inner refinement: reference residual level to reach
+  ST_BEST = 15,      // inner refinement: best residual seen
+};
+constexpr int kStatusLen = 16;
+
+// y / z pass geometry.  mode 0 (y): lines are contiguous rows of length L = N2,
+// a tile is TX rows.  mode 1 (z): lines run along h3 with stride N2, a tile is TX
+// adjacent h2 columns of one (comp, h1) plane; nlines then counts planes.
+struct LinesGeo {
+  int mode;
+  int L;
+  int TX;
+  int tiles_per_plane;
+  long long nlines;
+  int N2, N3;
+  int which;             // 0: spec (12 comps) ; 1: u[parity] (3 comps)
+  int parity;
+};
+
+// fused x pass geometry
+struct XGeo {
+  int N1, N2, N3, H1, H1p, TY, M;
+  long long S;
+  double invN;
+  int fields;            // write real-space eps/sigma (T1/T2 averages)
+};
+
+struct FinGeo {
+  int nbx, nbq;
+  double invN;
+  int parity;
+  int mode;              // 0 plain iteration, 1 FP64 sweep, 2 inner refinement iteration
+  int inner_max;
+};
+
+}  // namespace hz

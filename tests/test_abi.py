@@ -1,0 +1,110 @@
+"""C ABI: the library loads, exports every declared symbol, and its host-only
+logic (argument checks, sizes, workspace layout, reference-medium rule) works
+without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import hz_synth as syn
+import paper_2405_11168_amd as hz
+from paper_2405_11168_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "hz.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\*]+\s+)+\**(hz_\w+)\s*\(", src, re.M)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = hz.lib()
+    names = declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _abi.SIGNATURES, n
+
+
+def test_size_checks():
+    lib = hz.lib()
+    h = ctypes.c_void_p()
+    assert lib.hz_create_grid(16, 16, 15, ctypes.byref(h)) == _abi.HZ_EODD
+    assert lib.hz_create_grid(22, 16, 16, ctypes.byref(h)) == _abi.HZ_EINVAL  # prime 11
+    assert lib.hz_create_grid(0, 16, 16, ctypes.byref(h)) == _abi.HZ_EINVAL
+    assert lib.hz_create_grid(16, 16, 16, None) == _abi.HZ_EINVAL
+    assert b"NULL" in lib.hz_last_error()
+    for shape in [(2, 2, 2), (6, 10, 14), (320, 192, 192), (256, 256, 256)]:
+        g = hz.Grid(*shape)
+        assert g.workspace_bytes(hz.HZ_FP64, 1) > 0
+
+
+def test_material_validation():
+    g = hz.Grid(4, 4, 6)
+    C = np.stack([syn.isotropic_voigt(1, 0.3), syn.isotropic_voigt(2, 0.3)])
+    ph = np.zeros((6, 4, 4), dtype=np.uint16)
+    g.set_material(C, ph)
+    bad = C.copy()
+    bad[1, 0, 0] = -5.0
+    with pytest.raises(hz.HzError) as e:
+        g.set_material(bad, ph)
+    assert e.value.code == _abi.HZ_ENOTSPD
+    ph2 = ph.copy()
+    ph2[0, 0, 0] = 7
+    with pytest.raises(hz.HzError) as e:
+        g.set_material(C, ph2)
+    assert e.value.code == _abi.HZ_EINVAL
+    # voids (zero stiffness) are accepted
+    C0 = C.copy()
+    C0[1] = 0.0
+    g.set_material(C0, ph)
+
+
+def test_solve_without_workspace_is_rejected():
+    lib = hz.lib()
+    h = ctypes.c_void_p()
+    assert lib.hz_create_grid(4, 4, 4, ctypes.byref(h)) == 0
+    o = _abi.hz_opts()
+    lib.hz_default_opts(ctypes.byref(o))
+    E = np.zeros(6)
+    rc = lib.hz_solve(h, 1, E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(o), None, None,
+                      None, None)
+    assert rc == _abi.HZ_ENOMATERIAL
+    C = syn.isotropic_voigt(1, 0.3)
+    ph = np.zeros(64, dtype=np.uint16)
+    assert lib.hz_set_material(h, 1, C.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ph.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))) == 0
+    rc = lib.hz_solve(h, 1, E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(o), None, None,
+                      None, None)
+    assert rc == _abi.HZ_EWORKSPACE
+    lib.hz_destroy_grid(h)
+
+
+def test_workspace_scales_with_loads_and_precision():
+    g = hz.Grid(64, 48, 40)
+    a1 = g.workspace_bytes(hz.HZ_FP64, 1)
+    a6 = g.workspace_bytes(hz.HZ_FP64, 6)
+    S = (64 // 2 + 1) * 48 * 40
+    # per load: 12 spectra + 2 displacement buffers, FP64 complex (+ small status blocks)
+    per = (12 + 6) * S * 16
+    assert per <= (a6 - a1) / 5 < 1.02 * per
+    r1 = g.workspace_bytes(hz.HZ_FP32_REFINE, 1)
+    r2 = g.workspace_bytes(hz.HZ_FP32_REFINE, 2)
+    per = (12 * 16 + 6 * 8 + 3 * 16 + 3 * 8) * S
+    assert per <= r2 - r1 < 1.02 * per
+
+
+def test_reference_medium_rule():
+    """Automatic reference: isotropic, nu0 = 0, Mandel modulus at the midpoint of the
+    extreme Mandel eigenvalues over all phases."""
+    rng = np.random.default_rng(0)
+    C = np.stack([syn.random_spd_voigt(rng, 0.5, 3.0), syn.random_spd_voigt(rng, 2.0, 40.0)])
+    s = np.array([1, 1, 1, 2 ** .5, 2 ** .5, 2 ** .5])
+    ev = np.concatenate([np.linalg.eigvalsh(c * np.outer(s, s)) for c in C])
+    m = 0.5 * (ev.min() + ev.max())
+    C0 = hz.reference_medium(C)
+    expect = np.diag([m, m, m, m / 2, m / 2, m / 2])
+    assert np.abs(C0 - expect).max() < 1e-10 * m
