@@ -46,10 +46,10 @@ def kernel_bytes(kind, S, N, nloads, csz):
     """Algorithmic HBM bytes of one launch of a pass over `nloads` problems:
     complex spectra moved (S complex elements per component, csz bytes each)."""
     units = {
-        "expand": 3 + 12,          # read u (3), write 12 strain spectra
-        "lines_z_inv": 24, "lines_y_inv": 24, "lines_y_fwd": 24, "lines_z_fwd": 24,
+        "zexpand": 3 + 12,         # read u (3), write 12 strain spectra
+        "yinv": 24, "yfwd": 24,    # read 12, write 12
         "xpass": 24,               # read 12, write 12 (+ phase map)
-        "contract": 12 + 3 + 3,    # read 12 stress spectra + u, write u
+        "zcontract": 12 + 3 + 3,   # read 12 stress spectra + u, write u
     }
     if kind not in units:
         return None

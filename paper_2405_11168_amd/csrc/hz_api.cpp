@@ -20,16 +20,15 @@
 namespace hz {
 
 template <typename T>
-hipError_t launch_expand(const Desc*, const int*, int, int, int, const Geo&, const void*, const void*,
-                         const void*, hipStream_t);
+hipError_t launch_zexp(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*,
+                       hipStream_t);
 template <typename T>
-hipError_t launch_lines(const Desc*, const int*, int, const LinesGeo&, const Plan&, const void*, bool,
-                        hipStream_t);
+hipError_t launch_yline(const Desc*, const int*, int, const YGeo&, const Plan*, const void*, bool, hipStream_t);
 template <typename T>
-hipError_t launch_xpass(const Desc*, const int*, int, const XGeo&, const Plan&, const void*, hipStream_t);
+hipError_t launch_xpass(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
 template <typename T>
-hipError_t launch_contract(int, const Desc*, const int*, int, int, const Geo&, const void*, const void*,
-                           const void*, hipStream_t);
+hipError_t launch_zcon(int, const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*,
+                       const void*, const void*, hipStream_t);
 hipError_t launch_finalize(const Desc*, const int*, int, const FinGeo&, hipStream_t);
 hipError_t launch_accumulate(const Desc*, const int*, int, long long, hipStream_t);
 hipError_t launch_zero(const Desc*, const int*, int, int, long long, hipStream_t);
@@ -68,6 +67,7 @@ Plan make_plan(int L) {
   p.np = 0;
   int n = L;
   auto push = [&](int r) { p.radix[p.np++] = r; n /= r; };
+  while (n % 16 == 0) push(16);
   while (n % 8 == 0) push(8);
   while (n % 4 == 0) push(4);
   while (n % 2 == 0) push(2);
@@ -87,9 +87,8 @@ int divisor_le(int n, int cap) {
   return 1;
 }
 
-const char* kKindNames[] = {"expand",   "lines_z_inv", "lines_y_inv", "xpass",      "lines_y_fwd",
-                            "lines_z_fwd", "contract", "finalize",    "accumulate", "zero"};
-enum Kind { K_EXPAND, K_ZINV, K_YINV, K_XPASS, K_YFWD, K_ZFWD, K_CONTRACT, K_FINAL, K_ACCUM, K_ZERO, K_COUNT };
+const char* kKindNames[] = {"zexpand", "yinv", "xpass", "yfwd", "zcontract", "finalize", "accumulate", "zero"};
+enum Kind { K_ZEXP, K_YINV, K_XPASS, K_YFWD, K_ZCON, K_FINAL, K_ACCUM, K_ZERO, K_COUNT };
 
 }  // namespace
 
@@ -103,7 +102,7 @@ struct hz_grid_s {
   // tiling
   Plan plan1{}, plan2{}, plan3{}, planM{};
   int TXz[2]{}, TXy[2]{}, TYx[2]{}, H1p[2]{};  // [0]=FP32, [1]=FP64
-  long long nbx[2]{}, nbq = 0;
+  long long nbx[2]{}, nbq[2]{};
 
   // bound workspace
   char* ws = nullptr;
@@ -112,7 +111,7 @@ struct hz_grid_s {
   int prec = -1;
   int cap = 0;
   struct Off {
-    size_t tw64[3], tw32[3], C64, C32, phase, descs, active, status, status2, part_sig, part_res, trace, fields;
+    size_t tw64[3], tw32[3], plans, C64, C32, phase, descs, active, status, status2, part_sig, part_res, trace, fields;
     std::vector<size_t> spec, u0, u1, u64, r32;
     size_t total;
   } off;
@@ -144,26 +143,28 @@ void compute_tiling(hz_grid g) {
   g->planM = make_plan(G.N1 / 2);
   for (int d = 0; d < 2; ++d) {
     const int csz = d ? 16 : 8;
-    const int emax = d ? 8 : 16;  // elements per thread in one in-LDS transform
-    const int maxel = kLdsBytes / csz;
-    if (std::max(G.N2, G.N3) > emax * kThreads || G.N1 / 2 > emax * kThreads)
-      fail(HZ_EINVAL, "line too long for the LDS transform");
-    // z: TX adjacent h2 columns, TX | N2, rows of TX*csz bytes
-    g->TXz[d] = divisor_le(G.N2, std::max(1, std::min(256 / csz, maxel / G.N3)));
-    if (G.N3 > maxel) fail(HZ_EINVAL, "N3 too large for the LDS transform");
-    g->TXy[d] = std::max(1, std::min(32, maxel / G.N2));
-    if (G.N2 > maxel) fail(HZ_EINVAL, "N2 too large for the LDS transform");
-    // x: 6 comps x TY rows x (N1/2+1) in LDS, 6*TY*M elements in the transform
-    int hp = G.H1 | 1;  // odd pitch spreads rows across LDS banks
-    int ty = 16;
-    while (ty > 1 && 6 * ty * hp * csz > kLdsBytes) --ty;
-    ty = divisor_le(G.N2, ty);
-    if (6 * ty * hp * csz > kLdsBytes) fail(HZ_EINVAL, "N1 too large for the fused x pass");
-    g->TYx[d] = ty;
+    const int tile = 16 * kThreads;             // elements per transform call (emax)
+    const int rowcap = 256 / csz;               // TX giving 256-byte rows
+    // z kernels: 3 comps x TX columns x N3 in LDS (+ N3 twiddles), TX | N2
+    int tx = std::min(rowcap, G.N2);
+    while (tx > 1 && (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes || G.N2 % tx)) --tx;
+    if (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes) fail(HZ_EINVAL, "N3 too large");
+    g->TXz[d] = tx;
+    // y kernel: TX rows of N2 (+ N2 twiddles)
+    int ty = std::min(64, tile / G.N2);
+    while (ty > 1 && (ty * G.N2 + G.N2) * csz > kLdsBytes) --ty;
+    if (ty < 1 || G.N2 > tile || (ty * G.N2 + G.N2) * csz > kLdsBytes) fail(HZ_EINVAL, "N2 too large");
+    g->TXy[d] = ty;
+    // x kernel: 6 comps x TY rows x (N1/2+1) in LDS (+ N1 twiddles), TY | N2
+    const int hp = G.H1 | 1;  // odd pitch spreads rows across LDS banks
+    int tyx = std::min(16, G.N2);
+    while (tyx > 1 && ((6 * tyx * hp + G.N1) * csz > kLdsBytes || 6 * tyx * (G.N1 / 2) > tile || G.N2 % tyx)) --tyx;
+    if ((6 * tyx * hp + G.N1) * csz > kLdsBytes || 6 * tyx * (G.N1 / 2) > tile) fail(HZ_EINVAL, "N1 too large");
+    g->TYx[d] = tyx;
     g->H1p[d] = hp;
-    g->nbx[d] = (long long)G.N3 * (G.N2 / ty);
+    g->nbx[d] = 2LL * G.N3 * (G.N2 / tyx);
+    g->nbq[d] = (long long)G.H1 * (G.N2 / tx);
   }
-  g->nbq = (G.S + kThreads - 1) / kThreads;
 }
 
 void layout(hz_grid g, int prec, int nl, hz_grid_s::Off& o) {
@@ -173,6 +174,7 @@ void layout(hz_grid g, int prec, int nl, hz_grid_s::Off& o) {
   const int Ns[3] = {G.N1, G.N2, G.N3};
   for (int a = 0; a < 3; ++a) o.tw64[a] = take((size_t)Ns[a] * 16);
   for (int a = 0; a < 3; ++a) o.tw32[a] = take((size_t)Ns[a] * 8);
+  o.plans = take(4 * sizeof(Plan));  // N1, N2, N3, N1/2
   const int np = std::max(1, g->n_phases);
   o.C64 = take((size_t)np * 36 * 8);
   o.C32 = take((size_t)np * 36 * 4);
@@ -183,7 +185,7 @@ void layout(hz_grid g, int prec, int nl, hz_grid_s::Off& o) {
   o.status2 = take((size_t)nl * kStatusLen * 8);
   const long long nbx = std::max(g->nbx[0], g->nbx[1]);
   o.part_sig = take((size_t)nl * nbx * 6 * 8);
-  o.part_res = take((size_t)nl * g->nbq * 8);
+  o.part_res = take((size_t)nl * std::max(g->nbq[0], g->nbq[1]) * 8);
   o.trace = take((size_t)nl * kTraceCap * 7 * 8);
   o.fields = take((size_t)12 * G.N * 8);
   o.spec.assign(nl, 0);
@@ -223,6 +225,8 @@ void upload_tables(hz_grid g) {
     hip_check(hipMemcpy(g->ws + g->off.tw64[a], t64.data(), t64.size() * 8, hipMemcpyHostToDevice), "upload twiddles");
     hip_check(hipMemcpy(g->ws + g->off.tw32[a], t32.data(), t32.size() * 4, hipMemcpyHostToDevice), "upload twiddles");
   }
+  const Plan plans[4] = {g->plan1, g->plan2, g->plan3, g->planM};
+  hip_check(hipMemcpy(g->ws + g->off.plans, plans, sizeof(plans), hipMemcpyHostToDevice), "upload plans");
   std::vector<float> c32(g->C.size());
   for (size_t i = 0; i < c32.size(); ++i) c32[i] = (float)g->C[i];
   hip_check(hipMemcpy(g->ws + g->off.C64, g->C.data(), g->C.size() * 8, hipMemcpyHostToDevice), "upload C");
@@ -359,7 +363,7 @@ struct Ctx {
   int nact;
 };
 
-// One pass through the 12-field pipeline (P1..P4) in precision T, expand source src.
+// P1 (expand + inverse z) and P2 (inverse y) in precision T; src 0 = u[parity], 1 = u64
 template <typename T>
 void pipeline_front(Ctx& c, int parity, int src) {
   hz_grid g = c.g;
@@ -367,16 +371,14 @@ void pipeline_front(Ctx& c, int parity, int src) {
   const int d = sizeof(T) == 8;
   const size_t* tw = d ? g->off.tw64 : g->off.tw32;
   Launcher L{g};
-  L.begin(K_EXPAND, d);
-  L.end(launch_expand<T>(c.dd, c.act, c.nact, parity, src, G, g->ws + g->off.tw64[0], g->ws + g->off.tw64[1],
-                         g->ws + g->off.tw64[2], g->stream),
-        "expand");
-  LinesGeo z{1, G.N3, g->TXz[d], G.N2 / g->TXz[d], (long long)12 * G.H1, G.N2, G.N3, 0, 0};
-  L.begin(K_ZINV, d);
-  L.end(launch_lines<T>(c.dd, c.act, c.nact, z, g->plan3, g->ws + tw[2], true, g->stream), "z inverse");
-  LinesGeo y{0, G.N2, g->TXy[d], 0, (long long)12 * G.H1 * G.N3, G.N2, G.N3, 0, 0};
+  ZGeo zg{G.N1, G.N2, G.N3, G.H1, g->TXz[d], G.N2 / g->TXz[d], G.S, parity, src};
+  L.begin(K_ZEXP, d);
+  L.end(launch_zexp<T>(c.dd, c.act, c.nact, zg, P<Plan>(g, g->off.plans) + 2, g->ws + tw[2], g->ws + g->off.tw64[0],
+                       g->ws + g->off.tw64[1], g->stream),
+        "z expand");
+  YGeo yg{G.N2, g->TXy[d], (long long)12 * G.H1 * G.N3};
   L.begin(K_YINV, d);
-  L.end(launch_lines<T>(c.dd, c.act, c.nact, y, g->plan2, g->ws + tw[1], true, g->stream), "y inverse");
+  L.end(launch_yline<T>(c.dd, c.act, c.nact, yg, P<Plan>(g, g->off.plans) + 1, g->ws + tw[1], true, g->stream), "y inverse");
 }
 
 template <typename T>
@@ -385,12 +387,16 @@ void pipeline_x(Ctx& c, int fields) {
   const Geo& G = g->geo;
   const int d = sizeof(T) == 8;
   const size_t* tw = d ? g->off.tw64 : g->off.tw32;
-  XGeo xg{G.N1, G.N2, G.N3, G.H1, g->H1p[d], g->TYx[d], G.N1 / 2, G.S, 1.0 / (double)G.N, fields};
   Launcher L{g};
-  L.begin(K_XPASS, d);
-  L.end(launch_xpass<T>(c.dd, c.act, c.nact, xg, g->planM, g->ws + tw[0], g->stream), "x pass");
+  // with fields, T1 writes and T2 then adds its half of the averages: two launches
+  for (int h = fields ? 0 : -1; h < (fields ? 2 : 0); ++h) {
+    XGeo xg{G.N1, G.N2, G.N3, G.H1, g->H1p[d], g->TYx[d], G.N1 / 2, G.S, 1.0 / (double)G.N, fields, h};
+    L.begin(K_XPASS, d);
+    L.end(launch_xpass<T>(c.dd, c.act, c.nact, xg, P<Plan>(g, g->off.plans) + 3, g->ws + tw[0], g->stream), "x pass");
+  }
 }
 
+// P4 (forward y) and P5 (forward z + contraction + update); mode as k_zcon
 template <typename T>
 void pipeline_back(Ctx& c, int parity, int mode) {
   hz_grid g = c.g;
@@ -398,21 +404,19 @@ void pipeline_back(Ctx& c, int parity, int mode) {
   const int d = sizeof(T) == 8;
   const size_t* tw = d ? g->off.tw64 : g->off.tw32;
   Launcher L{g};
-  LinesGeo y{0, G.N2, g->TXy[d], 0, (long long)12 * G.H1 * G.N3, G.N2, G.N3, 0, 0};
+  YGeo yg{G.N2, g->TXy[d], (long long)12 * G.H1 * G.N3};
   L.begin(K_YFWD, d);
-  L.end(launch_lines<T>(c.dd, c.act, c.nact, y, g->plan2, g->ws + tw[1], false, g->stream), "y forward");
-  LinesGeo z{1, G.N3, g->TXz[d], G.N2 / g->TXz[d], (long long)12 * G.H1, G.N2, G.N3, 0, 0};
-  L.begin(K_ZFWD, d);
-  L.end(launch_lines<T>(c.dd, c.act, c.nact, z, g->plan3, g->ws + tw[2], false, g->stream), "z forward");
-  L.begin(K_CONTRACT, d);
-  L.end(launch_contract<T>(mode, c.dd, c.act, c.nact, parity, G, g->ws + g->off.tw64[0], g->ws + g->off.tw64[1],
-                           g->ws + g->off.tw64[2], g->stream),
-        "contract");
+  L.end(launch_yline<T>(c.dd, c.act, c.nact, yg, P<Plan>(g, g->off.plans) + 1, g->ws + tw[1], false, g->stream), "y forward");
+  ZGeo zg{G.N1, G.N2, G.N3, G.H1, g->TXz[d], G.N2 / g->TXz[d], G.S, parity, 0};
+  L.begin(K_ZCON, d);
+  L.end(launch_zcon<T>(mode, c.dd, c.act, c.nact, zg, P<Plan>(g, g->off.plans) + 2, g->ws + tw[2], g->ws + g->off.tw64[0],
+                       g->ws + g->off.tw64[1], g->ws + g->off.tw64[2], g->stream),
+        "z contract");
 }
 
 void finalize(Ctx& c, int parity, int mode, int dbl, int inner_max = 0) {
   hz_grid g = c.g;
-  FinGeo fg{(int)g->nbx[dbl], (int)g->nbq, 1.0 / (double)g->geo.N, parity, mode, inner_max};
+  FinGeo fg{(int)g->nbx[dbl], (int)g->nbq[dbl], 1.0 / (double)g->geo.N, parity, mode, inner_max};
   Launcher L{g};
   L.begin(K_FINAL, dbl);
   L.end(launch_finalize(c.dd, c.act, c.nact, fg, g->stream), "finalize");
@@ -437,7 +441,7 @@ Desc base_desc(hz_grid g, int b, const double* E, const double* C0t, double tol,
   d.C32 = P<float>(g, o.C32);
   const int dbl = (g->prec == HZ_FP64 || !inner) ? 1 : 0;
   d.part_sig = P<double>(g, o.part_sig) + (size_t)b * std::max(g->nbx[0], g->nbx[1]) * 6;
-  d.part_res = P<double>(g, o.part_res) + (size_t)b * g->nbq;
+  d.part_res = P<double>(g, o.part_res) + (size_t)b * std::max(g->nbq[0], g->nbq[1]);
   d.status = P<double>(g, inner ? o.status2 : o.status) + (size_t)b * kStatusLen;
   d.eps_out = P<double>(g, o.fields);
   d.sig_out = P<double>(g, o.fields) + 6 * g->geo.N;

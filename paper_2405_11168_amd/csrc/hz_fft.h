@@ -1,5 +1,10 @@
-// Complex arithmetic, radix butterflies and the LDS-resident Stockham transform
-// used by every FFT pass of the solver (gfx950, wave64).
+// Complex arithmetic, radix butterflies and the Stockham line transforms used by
+// every FFT pass of the solver (gfx950, wave64).
+//
+// A transform of `lines` lines of length L = prod(radix) runs as Stockham
+// passes.  The first pass may read straight from global memory and the last
+// pass may write straight to global memory, so a two-pass length (e.g.
+// 128 = 16 x 8) touches LDS once: HBM -> registers -> LDS -> registers -> HBM.
 #pragma once
 #include "hz_internal.h"
 
@@ -50,6 +55,15 @@ template <> struct Trig<7> {
                                   0.43388373911755812048, -0.43388373911755812048,
                                   -0.97492791218182360702, -0.78183148246802980871};
 };
+// cos/sin(2 pi e / 16), e = 0..9 (the exponents a radix-16 butterfly needs)
+struct Trig16 {
+  static constexpr double c[10] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0,
+                                   -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613, -1.0,
+                                   -0.92387953251128675613};
+  static constexpr double s[10] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613, 1.0,
+                                   0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0,
+                                   -0.38268343236508977173};
+};
 
 // In-register DFT of length R: a[k] <- sum_n a[n] exp(-+2 pi i n k / R)
 template <typename T, int R, bool INV> struct Dft;
@@ -94,6 +108,35 @@ template <typename T, bool INV> struct Dft<T, 8, INV> {
   }
 };
 
+// 16 = 4 x 4: DFT4 over n1 (stride 4), twiddle w16^(n2 k1), DFT4 over n2
+template <typename T, bool INV> struct Dft<T, 16, INV> {
+  static __device__ __forceinline__ void run(cpx<T>* a) {
+    cpx<T> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cpx<T> z[4] = {a[n2], a[n2 + 4], a[n2 + 8], a[n2 + 12]};
+      Dft<T, 4, INV>::run(z);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) {
+        const int e = n2 * k1;
+        if (e == 0) {
+          y[n2][k1] = z[k1];
+        } else {
+          const cpx<T> w = {(T)Trig16::c[e], INV ? (T)Trig16::s[e] : -(T)Trig16::s[e]};
+          y[n2][k1] = z[k1] * w;
+        }
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cpx<T> z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      Dft<T, 4, INV>::run(z);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = z[k2];
+    }
+  }
+};
+
 // odd prime radix: X_k = a0 + sum_{n<=h} [c(nk)(a_n + a_{R-n}) -+ i s(nk)(a_n - a_{R-n})]
 template <typename T, int R, bool INV> struct DftOdd {
   static __device__ __forceinline__ void run(cpx<T>* a) {
@@ -132,37 +175,73 @@ template <typename T, bool INV> struct Dft<T, 3, INV> : DftOdd<T, 3, INV> {};
 template <typename T, bool INV> struct Dft<T, 5, INV> : DftOdd<T, 5, INV> {};
 template <typename T, bool INV> struct Dft<T, 7, INV> : DftOdd<T, 7, INV> {};
 
-// One Stockham radix-R pass over `lines` transforms of length L held in LDS.
-// Element (t, j) of line t sits at buf[t*sL + j*sJ].  Ns = product of the
-// radices already applied.  Inputs j, j+L/R, ..., outputs (j/Ns)*Ns*R + j%Ns + m*Ns.
-// Every thread keeps its butterflies in registers across one barrier, so the
-// pass is in place.  Twiddles come from tw[] = exp(-2 pi i n / (L*tstride)).
-template <typename T, int R, int BMAX, bool INV>
-__device__ __forceinline__ void stockham_pass(cpx<T>* buf, int L, int Ns, int lines, int sL,
-                                              int sJ, bool jfast, const cpx<T>* __restrict__ tw,
-                                              int tstride) {
+// ---------------------------------------------------------------------------
+// element accessors: get(t, j) / put(t, j, v) for element j of line t
+// ---------------------------------------------------------------------------
+template <typename T>
+struct LdsAcc {
+  static constexpr bool kLds = true;
+  cpx<T>* buf;
+  int sL, sJ;
+  __device__ __forceinline__ cpx<T> get(int t, int j) const { return buf[t * sL + j * sJ]; }
+  __device__ __forceinline__ void put(int t, int j, cpx<T> v) const { buf[t * sL + j * sJ] = v; }
+};
+
+// global line storage: element (t, j) at p[(t / G) * B + (t % G) * sl + j * sj]
+// (32-bit offsets: a problem's spectra stay below 2^31 elements)
+template <typename T>
+struct GblAcc {
+  static constexpr bool kLds = false;
+  cpx<T>* p;
+  int B, G, sl, sj;
+  __device__ __forceinline__ int at(int t, int j) const {
+    const int q = t / G;
+    return q * B + (t - q * G) * sl + j * sj;
+  }
+  __device__ __forceinline__ cpx<T> get(int t, int j) const { return p[at(t, j)]; }
+  __device__ __forceinline__ void put(int t, int j, cpx<T> v) const { p[at(t, j)] = v; }
+};
+
+__device__ __forceinline__ void line_map(int b, int lines, int LR, bool jfast, int& t, int& j) {
+  if (jfast) {
+    t = b / LR;
+    j = b - t * LR;
+  } else {
+    j = b / lines;
+    t = b - j * lines;
+  }
+}
+
+// One radix-R Stockham pass: inputs j, j+L/R, ...; outputs (j/Ns)*Ns*R + j%Ns + m*Ns.
+// Twiddles exp(-+2 pi i m k / (Ns R)) come from tw[] = exp(-2 pi i n / (L*tstride)).
+// `inplace` puts a barrier between reading src and writing dst (same LDS buffer).
+template <typename T, int R, int BMAX, bool INV, class SRC, class DST>
+__device__ __forceinline__ void pass_gen(int L, int Ns, int lines, bool jfast, const cpx<T>* __restrict__ tw,
+                                         int tstride, const SRC& src, const DST& dst, bool inplace) {
   const int LR = L / R;
   const int nb = lines * LR;
   const int tid = threadIdx.x;
-  cpx<T> v[BMAX][R];
   const int span = Ns * R;
   const int tws = (L / span) * tstride;
+  cpx<T> v[BMAX][R];
 #pragma unroll
   for (int i = 0; i < BMAX; ++i) {
     const int b = tid + i * kThreads;
     if (b < nb) {
       int t, j;
-      if (jfast) {
-        t = b / LR;
-        j = b - t * LR;
-      } else {
-        j = b / lines;
-        t = b - j * lines;
-      }
-      const int k = j % Ns;
+      line_map(b, lines, LR, jfast, t, j);
 #pragma unroll
-      for (int m = 0; m < R; ++m) v[i][m] = buf[t * sL + (j + m * LR) * sJ];
+      for (int m = 0; m < R; ++m) v[i][m] = src.get(t, j + m * LR);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < BMAX; ++i) {
+    const int b = tid + i * kThreads;
+    if (b < nb) {
       if (Ns > 1) {
+        int t, j;
+        line_map(b, lines, LR, jfast, t, j);
+        const int k = j % Ns;
 #pragma unroll
         for (int m = 1; m < R; ++m) {
           cpx<T> w = tw[m * k * tws];
@@ -173,65 +252,87 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* buf, int L, int Ns, int li
       Dft<T, R, INV>::run(v[i]);
     }
   }
-  __syncthreads();
+  if (inplace) __syncthreads();
 #pragma unroll
   for (int i = 0; i < BMAX; ++i) {
     const int b = tid + i * kThreads;
     if (b < nb) {
       int t, j;
-      if (jfast) {
-        t = b / LR;
-        j = b - t * LR;
-      } else {
-        j = b / lines;
-        t = b - j * lines;
-      }
+      line_map(b, lines, LR, jfast, t, j);
       const int k = j % Ns;
       const int base = (j / Ns) * span + k;
 #pragma unroll
-      for (int m = 0; m < R; ++m) buf[t * sL + (base + m * Ns) * sJ] = v[i][m];
+      for (int m = 0; m < R; ++m) dst.put(t, base + m * Ns, v[i][m]);
     }
   }
+}
+
+template <int EMAX, int R>
+constexpr int bmax() { return (EMAX + R - 1) / R; }
+
+template <typename T, int EMAX, bool INV, class SRC, class DST>
+__device__ __forceinline__ void pass_any(int R, int L, int Ns, int lines, bool jfast, const cpx<T>* __restrict__ tw,
+                                         int tstride, const SRC& src, const DST& dst, bool inplace) {
+  switch (R) {
+    case 16: pass_gen<T, 16, bmax<EMAX, 16>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
+    case 8: pass_gen<T, 8, bmax<EMAX, 8>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
+    case 4: pass_gen<T, 4, bmax<EMAX, 4>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
+    case 2: pass_gen<T, 2, bmax<EMAX, 2>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
+    case 7: pass_gen<T, 7, bmax<EMAX, 7>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
+    case 5: pass_gen<T, 5, bmax<EMAX, 5>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
+    default: pass_gen<T, 3, bmax<EMAX, 3>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
+  }
+}
+
+// Whole transform of `lines` lines (lines * L <= EMAX * kThreads), unnormalised.
+// src -> [first pass] -> lds -> [middle passes] -> lds -> [last pass] -> dst.
+// The plan lists radices grouped 16s, 8s, 4s, 2s, 7s, 5s, 3s; the middle passes
+// run one loop per radix so each keeps its own register allocation.  When dst
+// is LDS the caller synchronises before reading it; when src is LDS the caller
+// synchronised after filling it.
+template <typename T, int EMAX, bool INV, class SRC, class DST>
+__device__ __forceinline__ void fft_lines(const Plan& plan, int lines, bool jfast, const cpx<T>* __restrict__ tw, int tstride,
+                          const LdsAcc<T>& lds, const SRC& src, const DST& dst) {
+  const int np = plan.np, L = plan.L;
+  if (np == 0) {  // L == 1: copy
+    for (int t = threadIdx.x; t < lines; t += kThreads) dst.put(t, 0, src.get(t, 0));
+    return;
+  }
+  if (np == 1) {
+    pass_any<T, EMAX, INV>(plan.radix[0], L, 1, lines, jfast, tw, tstride, src, dst, SRC::kLds && DST::kLds);
+    return;
+  }
+  pass_any<T, EMAX, INV>(plan.radix[0], L, 1, lines, jfast, tw, tstride, src, lds, SRC::kLds);
   __syncthreads();
-}
-
-// Full transform of `lines` lines of length plan.L in LDS (unnormalised).
-// EMAX bounds the elements per thread: lines * L <= EMAX * kThreads.  The plan
-// lists radices grouped as 8s, 4s, 2s, 7s, 5s, 3s; one loop per radix keeps the
-// register allocation of each pass separate.
-template <typename T, int EMAX, bool INV>
-__device__ void lds_fft(cpx<T>* buf, const Plan& plan, int lines, int sL, int sJ, bool jfast,
-                        const cpx<T>* __restrict__ tw, int tstride) {
-  int Ns = 1, s = 0;
-  const int L = plan.L;
-#define HZ_PASSES(R)                                                                            \
-  for (; s < plan.np && plan.radix[s] == R; ++s) {                                              \
-    stockham_pass<T, R, (EMAX + R - 1) / R, INV>(buf, L, Ns, lines, sL, sJ, jfast, tw, tstride); \
-    Ns *= R;                                                                                    \
+  int Ns = plan.radix[0], s = 1;
+#define HZ_MID(R)                                                                                   \
+  for (; s < np - 1 && plan.radix[s] == R; ++s) {                                                   \
+    pass_gen<T, R, bmax<EMAX, R>(), INV>(L, Ns, lines, jfast, tw, tstride, lds, lds, true);          \
+    __syncthreads();                                                                                \
+    Ns *= R;                                                                                        \
   }
-  HZ_PASSES(8)
-  HZ_PASSES(4)
-  HZ_PASSES(2)
-  HZ_PASSES(7)
-  HZ_PASSES(5)
-  HZ_PASSES(3)
-#undef HZ_PASSES
+  HZ_MID(16)
+  HZ_MID(8)
+  HZ_MID(4)
+  HZ_MID(2)
+  HZ_MID(7)
+  HZ_MID(5)
+  HZ_MID(3)
+#undef HZ_MID
+  pass_any<T, EMAX, INV>(plan.radix[np - 1], L, Ns, lines, jfast, tw, tstride, lds, dst, DST::kLds);
 }
 
-// Transform `lines` lines whose total may exceed EMAX*kThreads elements: the
-// lines are processed in chunks that each respect the per-thread bound.
-// Line t starts at buf + t*sL (element stride sJ).
-template <typename T, int EMAX, bool INV>
-__device__ void lds_fft_chunked(cpx<T>* buf, const Plan& plan, int lines, int sL, int sJ, bool jfast,
-                                const cpx<T>* __restrict__ tw, int tstride) {
-  const int per = max(1, (EMAX * kThreads) / plan.L);
-  for (int t0 = 0; t0 < lines; t0 += per) {
-    const int n = min(per, lines - t0);
-    lds_fft<T, EMAX, INV>(buf + t0 * sL, plan, n, sL, sJ, jfast, tw, tstride);
-  }
-}
-
+// elements per thread in one transform call (bounds register use)
 template <typename T>
-constexpr int emax_of() { return sizeof(T) == 8 ? 8 : 16; }
+constexpr int emax() { return 16; }
+
+// Out-of-line copy for callers that run a transform inside a loop: inlining
+// there lets the compiler hoist every pass variant's index arithmetic out of the
+// loop and keep it live across the whole body.
+template <typename T, int EMAX, bool INV, class SRC, class DST>
+__device__ __noinline__ void fft_lines_call(const Plan* plan, int lines, bool jfast, const cpx<T>* __restrict__ tw,
+                                            int tstride, LdsAcc<T> lds, SRC src, DST dst) {
+  fft_lines<T, EMAX, INV>(*plan, lines, jfast, tw, tstride, lds, src, dst);
+}
 
 }  // namespace hz

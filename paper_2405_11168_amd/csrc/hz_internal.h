@@ -65,18 +65,19 @@ enum St {
 };
 constexpr int kStatusLen = 16;
 
-// y / z pass geometry.  mode 0 (y): lines are contiguous rows of length L = N2,
-// a tile is TX rows.  mode 1 (z): lines run along h3 with stride N2, a tile is TX
-// adjacent h2 columns of one (comp, h1) plane; nlines then counts planes.
-struct LinesGeo {
-  int mode;
-  int L;
-  int TX;
-  int tiles_per_plane;
-  long long nlines;
-  int N2, N3;
-  int which;             // 0: spec (12 comps) ; 1: u[parity] (3 comps)
+// z pass geometry (expand + inverse z, or forward z + contraction): a tile is TX
+// adjacent h2 columns of one h1 plane, all N3 elements, 3 displacement components.
+struct ZGeo {
+  int N1, N2, N3, H1, TX, tiles;   // tiles = N2 / TX
+  long long S;
   int parity;
+  int src;                          // k_zexp: 0 = u[parity], 1 = FP64 anchor u64
+};
+
+// y pass geometry: contiguous rows of length N2, TX rows per tile
+struct YGeo {
+  int N2, TX;
+  long long nlines;                 // 12 * H1 * N3
 };
 
 // fused x pass geometry
@@ -85,6 +86,7 @@ struct XGeo {
   long long S;
   double invN;
   int fields;            // write real-space eps/sigma (T1/T2 averages)
+  int half;              // -1: both tetrahedra (two blocks per row tile); 0/1: only T1/T2
 };
 
 struct FinGeo {

@@ -1,12 +1,16 @@
 // HIP kernels (gfx950) of one iteration of the tetrahedral-stencil basic scheme.
 //
-// Iteration (Algorithm 1, Sec. 2.6), spectra stored as [comp][h1][h3][h2]:
-//   k_expand    u(q) -> 12 strain spectra  eps^T1 = D~ (x)_s u, eps^T2 = D~2 (x)_s u
-//   k_lines     inverse z, inverse y            (LDS Stockham, batched over comps)
+// Spectra are stored [comp][h1][h3][h2] (h1 in [0, N1/2], h2 fastest).  Iteration
+// (Algorithm 1, Sec. 2.6):
+//   k_zexp      u(q) (3 comps) -> inverse z transform of the 3 displacement comps,
+//               then the 12 strain comps eps^T1 = D~ (x)_s u, eps^T2 = D~2 (x)_s u
+//               formed in the mixed (h1, h2, l3) domain
+//   k_yline     inverse y (12 comps)
 //   k_xpass     per (l3, l2-tile): C2R along x, sigma = C(phase):(Ebar + eps), R2C along x,
 //               FP64 partial sums of <sigma>
-//   k_lines     forward y, forward z
-//   k_contract  r = sigma^T1.conj(D~) + sigma^T2.conj(D~2), Omega(q) in FP64, u update,
+//   k_yline     forward y
+//   k_zcon      r = sigma^T1.conj(D~) + sigma^T2.conj(D~2) formed in the mixed domain,
+//               forward z transform of its 3 comps, Omega(q) in FP64, u update,
 //               FP64 partial sums of w |r/2|^2
 //   k_finalize  fixed-order sums, eps_k = L2/||<sigma>||, device-side stop rule
 //
@@ -17,6 +21,17 @@
 // other four corners (eqs. Dq, DA1-DA2), both periodic in h, and the update
 // u~ <- u~ - Omega r~ is the paper's update multiplied by the same phase
 // (Omega is real).  Outputs in real space do not see the phase at all.
+//
+// Why the z transforms run on 3 fields.  With t_a = exp(-i q_a) every component
+// of D~ and D~2 is affine in t3:  D~ = alpha + t3 beta, with alpha, beta functions
+// of (h1, h2) only:
+//   D~  = 1/2 (P, P, S)  + t3 1/2 (Q, -Q, -R)      P = 1 - t1 t2, Q = t2 - t1,
+//   D~2 = 1/2 (Q, -Q, R) + t3 1/2 (P, P, -S)       S = 1 + t1 t2, R = t1 + t2.
+// Multiplying by t3 is a shift by one voxel along l3 after the inverse z
+// transform, and multiplying by conj(t3) a shift by -1 before the forward one.
+// So the 12 strain spectra are 2-tap combinations of the z-transformed 3
+// displacement components, and the residual's 3 components are 2-tap
+// combinations of the 12 stresses taken before the forward z transform.
 #include "hz_fft.h"
 
 namespace hz {
@@ -77,93 +92,112 @@ __device__ __forceinline__ cpx<double> to64(cpx<T> a) { return {(double)a.x, (do
 template <typename T>
 __device__ __forceinline__ cpx<T> fr64(cpx<double> a) { return {(T)a.x, (T)a.y}; }
 
+
+// Blocks are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8).  Map
+// them so that each XCD walks a contiguous range of tiles: neighbouring tiles
+// that share cache lines then meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+// coefficients of D~ = a1 + t3 b1 and D~2 = a2 + t3 b2 at (h1, h2)
+__device__ __forceinline__ void affine_symbols(cpx<double> t1, cpx<double> t2, cpx<double>* a1, cpx<double>* b1,
+                                               cpx<double>* a2, cpx<double>* b2) {
+  const cpx<double> one = {1.0, 0.0};
+  const cpx<double> t12 = t1 * t2;
+  const cpx<double> P = scale(one - t12, 0.5), Q = scale(t2 - t1, 0.5);
+  const cpx<double> S = scale(one + t12, 0.5), R = scale(t1 + t2, 0.5);
+  const cpx<double> mQ = {-Q.x, -Q.y}, mR = {-R.x, -R.y}, mS = {-S.x, -S.y};
+  a1[0] = P; a1[1] = P; a1[2] = S;
+  b1[0] = Q; b1[1] = mQ; b1[2] = mR;
+  a2[0] = Q; a2[1] = mQ; a2[2] = R;
+  b2[0] = P; b2[1] = P; b2[2] = mS;
+}
+
 // ----------------------------------------------------------------------------
-// P1: displacement spectrum -> 12 strain spectra (eqs. desp_T1_dep_Q, desp_T2_dep_Q)
-// src: 0 = u[parity] in kernel precision, 1 = FP64 anchor u64
+// P1: inverse z transform of u (3 comps) and the 12 strain spectra
+// (eqs. desp_T1_dep_Q, desp_T2_dep_Q) as 2-tap combinations along l3.
+// Tile: TX adjacent h2 columns of one h1 plane.  LDS: 3*TX lines x N3, then twiddles.
 // ----------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_expand(const Desc* __restrict__ descs,
-                                                     const int* __restrict__ active, int parity,
-                                                     int src, Geo g,
-                                                     const cpx<double>* __restrict__ tw1,
-                                                     const cpx<double>* __restrict__ tw2,
-                                                     const cpx<double>* __restrict__ tw3) {
+__global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ descs, const int* __restrict__ active,
+                                                   ZGeo zg, const Plan* __restrict__ plan3, const cpx<T>* __restrict__ tw3T,
+                                                   const cpx<double>* __restrict__ tw1,
+                                                   const cpx<double>* __restrict__ tw2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
-  const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-  if (idx >= g.S) return;
-  const int h2 = (int)(idx % g.N2);
-  const int h3 = (int)((idx / g.N2) % g.N3);
-  const int h1 = (int)(idx / ((long long)g.N2 * g.N3));
-  cpx<double> D1[3], D2[3];
-  symbols(tw1[h1], tw2[h2], tw3[h3], D1, D2);
-  cpx<double> u[3];
-  if (src == 1) {
+  const int TX = zg.TX, N2 = zg.N2, N3 = zg.N3;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int h1 = tile / zg.tiles;
+  const int h2_0 = (tile % zg.tiles) * TX;
+  const int lines = 3 * TX;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* twl = buf + lines * N3;
+  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
+  const long long plane = (long long)h1 * N3 * N2 + h2_0;
+  const LdsAcc<T> lds{buf, 1, lines};
+  const void* usrc = zg.src == 1 ? d.u64 : d.u[zg.parity];
+  const GblAcc<T> src{reinterpret_cast<cpx<T>*>(const_cast<void*>(usrc)) + plane, (int)zg.S, TX, 1, N2};
+  fft_lines<T, emax<T>(), true>(*plan3, lines, false, twl, 1, lds, src, lds);
+  __syncthreads();
+  cpx<T>* out = reinterpret_cast<cpx<T>*>(d.spec) + plane;
+  const cpx<double> t1 = tw1[h1];
+  for (int e = threadIdx.x; e < TX * N3; e += kThreads) {
+    const int col = e % TX, l3 = e / TX;
+    const int lm = l3 == 0 ? N3 - 1 : l3 - 1;
+    cpx<double> a1[3], b1[3], a2[3], b2[3];
+    affine_symbols(t1, tw2[h2_0 + col], a1, b1, a2, b2);
+    cpx<double> U[3], Um[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = ld<double>(d.u64, c * g.S + idx);
-  } else {
+    for (int c = 0; c < 3; ++c) {
+      U[c] = to64(lds.get(c * TX + col, l3));
+      Um[c] = to64(lds.get(c * TX + col, lm));
+    }
+    const long long o = (long long)l3 * N2 + col;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = to64(ld<T>(d.u[parity], c * g.S + idx));
-  }
-  // symmetric products in component order 11,22,33,23,13,12
+    for (int t = 0; t < 2; ++t) {
+      const cpx<double>* A = t == 0 ? a1 : a2;
+      const cpx<double>* B = t == 0 ? b1 : b2;
+      // G[i][j] = (D_i u_j) in the mixed domain = A_i U_j + B_i U_j(l3-1)
+      cpx<double> G[3][3];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const cpx<double>* D = t == 0 ? D1 : D2;
-    cpx<double> e[6];
-    e[0] = D[0] * u[0];
-    e[1] = D[1] * u[1];
-    e[2] = D[2] * u[2];
-    e[3] = scale(D[1] * u[2] + D[2] * u[1], 0.5);
-    e[4] = scale(D[0] * u[2] + D[2] * u[0], 0.5);
-    e[5] = scale(D[0] * u[1] + D[1] * u[0], 0.5);
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) st<T>(d.spec, (t * 6 + c) * g.S + idx, fr64<T>(e[c]));
+        for (int j = 0; j < 3; ++j) G[i][j] = A[i] * U[j] + B[i] * Um[j];
+      cpx<double> e6[6];
+      e6[0] = G[0][0];
+      e6[1] = G[1][1];
+      e6[2] = G[2][2];
+      e6[3] = scale(G[1][2] + G[2][1], 0.5);
+      e6[4] = scale(G[0][2] + G[2][0], 0.5);
+      e6[5] = scale(G[0][1] + G[1][0], 0.5);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out[(t * 6 + c) * zg.S + o] = fr64<T>(e6[c]);
+    }
   }
 }
 
 // ----------------------------------------------------------------------------
-// y / z passes: batched 1D transforms along a strided axis, LDS Stockham.
-// mode 0 (y): lines are contiguous rows of length L = N2; a tile is TX rows.
-// mode 1 (z): lines run along h3 with stride N2; a tile is TX adjacent h2 columns
-//             of one (comp, h1) plane, so every row of the tile is TX*16 B contiguous.
+// y pass: TX contiguous rows of length N2; first radix pass straight from HBM,
+// last radix pass straight to HBM, twiddles in LDS.
 // ----------------------------------------------------------------------------
-
 template <typename T, bool INV>
-__global__ __launch_bounds__(kThreads) void k_lines(const Desc* __restrict__ descs,
-                                                    const int* __restrict__ active, LinesGeo lg,
-                                                    Plan plan, const cpx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ descs, const int* __restrict__ active,
+                                                    YGeo yg, const Plan* __restrict__ plan2, const cpx<T>* __restrict__ tw2T) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
-  cpx<T>* data = reinterpret_cast<cpx<T>*>(lg.which == 0 ? d.spec : d.u[lg.parity]);
-  const int L = lg.L;
-  if (lg.mode == 0) {
-    const long long t0 = (long long)blockIdx.x * lg.TX;
-    const int lines = (int)((lg.nlines - t0) < lg.TX ? (lg.nlines - t0) : lg.TX);
-    cpx<T>* base = data + t0 * L;
-    const int n = lines * L;
-    for (int f = threadIdx.x; f < n; f += kThreads) buf[f] = base[f];
-    __syncthreads();
-    lds_fft_chunked<T, emax_of<T>(), INV>(buf, plan, lines, L, 1, true, tw, 1);
-    for (int f = threadIdx.x; f < n; f += kThreads) base[f] = buf[f];
-  } else {
-    const int TX = lg.TX;
-    const long long plane = blockIdx.x / lg.tiles_per_plane;
-    const int h2_0 = (blockIdx.x % lg.tiles_per_plane) * TX;
-    cpx<T>* base = data + plane * (long long)lg.N3 * lg.N2 + h2_0;
-    const int n = TX * L;
-    for (int f = threadIdx.x; f < n; f += kThreads) {
-      const int t = f % TX, j = f / TX;
-      buf[f] = base[(long long)j * lg.N2 + t];
-    }
-    __syncthreads();
-    lds_fft_chunked<T, emax_of<T>(), INV>(buf, plan, TX, 1, TX, false, tw, 1);
-    for (int f = threadIdx.x; f < n; f += kThreads) {
-      const int t = f % TX, j = f / TX;
-      base[(long long)j * lg.N2 + t] = buf[f];
-    }
-  }
+  const int N2 = yg.N2;
+  const long long t0 = (long long)blockIdx.x * yg.TX;
+  const int lines = (int)((yg.nlines - t0) < yg.TX ? (yg.nlines - t0) : yg.TX);
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* twl = buf + yg.TX * N2;
+  for (int i = threadIdx.x; i < N2; i += kThreads) twl[i] = tw2T[i];
+  const LdsAcc<T> lds{buf, N2, 1};
+  const GblAcc<T> g{reinterpret_cast<cpx<T>*>(d.spec) + t0 * N2, N2, 1, 0, 1};
+  fft_lines<T, emax<T>(), INV>(*plan2, lines, true, twl, 1, lds, g, g);
 }
 
 // ----------------------------------------------------------------------------
@@ -172,7 +206,6 @@ __global__ __launch_bounds__(kThreads) void k_lines(const Desc* __restrict__ des
 // as a complex transform of length M = N1/2, constitutive law per voxel,
 // R2C back (with the 1/N of eq. FT), store.  FP64 partials of <sigma>.
 // ----------------------------------------------------------------------------
-
 template <typename T>
 __device__ __forceinline__ void constitutive(const T* __restrict__ C, const double* Eb,
                                              const T (&de)[6], T (&s)[6]) {
@@ -192,30 +225,54 @@ __device__ __forceinline__ void constitutive(const T* __restrict__ C, const doub
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ descs,
                                                     const int* __restrict__ active, XGeo xg,
-                                                    Plan planM, const cpx<T>* __restrict__ twN1) {
+                                                    const Plan* __restrict__ planM, const cpx<T>* __restrict__ twN1) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   __shared__ double red[6 * 4];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
   const int tiles2 = xg.N2 / xg.TY;
-  const int l3 = blockIdx.x / tiles2;
-  const int l2_0 = (blockIdx.x % tiles2) * xg.TY;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  // one block per (row tile, tetrahedron): half 0 = T1 comps 0..5, half 1 = T2 comps 6..11
+  const int half = xg.half >= 0 ? xg.half : (tile & 1);
+  const int rt = xg.half >= 0 ? tile : (tile >> 1);
+  const int l3 = rt / tiles2;
+  const int l2_0 = (rt % tiles2) * xg.TY;
   const int TY = xg.TY, H1 = xg.H1, H1p = xg.H1p, M = xg.M;
   const long long N3N2 = (long long)xg.N3 * xg.N2;
   const long long rowoff = (long long)l3 * xg.N2 + l2_0;
   const T* C = sizeof(T) == 8 ? reinterpret_cast<const T*>(d.C64) : reinterpret_cast<const T*>(d.C32);
   const uint16_t* ph = d.phase + ((long long)l3 * xg.N2 + l2_0) * xg.N1;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* twl = buf + 6 * TY * H1p;
+  for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const int nload = 6 * TY * H1;
   const int nlines = 6 * TY;
   const int kh = M / 2 + 1;  // pair items per line
+  const LdsAcc<T> lds{buf, H1p, 1};
+  constexpr int NPT = 8;  // loads in flight per thread per batch
 
-  for (int half = 0; half < 2; ++half) {
+  {
     const cpx<T>* src = reinterpret_cast<const cpx<T>*>(d.spec) + (long long)half * 6 * xg.S;
-    for (int f = threadIdx.x; f < nload; f += kThreads) {
-      const int r = f % TY, k = (f / TY) % H1, c = f / (TY * H1);
-      buf[(c * TY + r) * H1p + k] = src[c * xg.S + k * N3N2 + rowoff + r];
+#pragma unroll 1
+    for (int f0 = 0; f0 < nload; f0 += NPT * kThreads) {
+      T re[NPT], im[NPT];
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int f = min(f0 + (int)threadIdx.x + i * kThreads, nload - 1);
+        const int r = f % TY, k = (f / TY) % H1, c = f / (TY * H1);
+        const cpx<T> v = src[c * xg.S + k * N3N2 + rowoff + r];
+        re[i] = v.x;
+        im[i] = v.y;
+      }
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int f = f0 + threadIdx.x + i * kThreads;
+        if (f < nload) {
+          const int r = f % TY, k = (f / TY) % H1, c = f / (TY * H1);
+          buf[(c * TY + r) * H1p + k] = cpx<T>{re[i], im[i]};
+        }
+      }
     }
     __syncthreads();
     // C2R split: Z[k] = X[k] + conj(X[M-k]) + i w^k (X[k] - conj(X[M-k])), w = exp(2 pi i / N1)
@@ -228,17 +285,18 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
       } else {
         const int k1 = kk, k2 = M - kk;
         const cpx<T> a = X[k1], b = X[k2];
-        const cpx<T> w1 = conjg(twN1[k1]);
+        const cpx<T> w1 = conjg(twl[k1]);
         const cpx<T> z1 = (a + conjg(b)) + mul_i(w1 * (a - conjg(b)));
         if (k2 != k1) {
-          const cpx<T> w2 = conjg(twN1[k2]);
+          const cpx<T> w2 = conjg(twl[k2]);
           X[k2] = (b + conjg(a)) + mul_i(w2 * (b - conjg(a)));
         }
         X[k1] = z1;
       }
     }
     __syncthreads();
-    lds_fft_chunked<T, emax_of<T>(), true>(buf, planM, nlines, H1p, 1, true, twN1, 2);
+    fft_lines<T, emax<T>(), true>(*planM, nlines, true, twl, 2, lds, lds, lds);
+    __syncthreads();
     // constitutive law on voxel pairs (2n, 2n+1): real / imaginary parts
     for (int it = threadIdx.x; it < TY * M; it += kThreads) {
       const int r = it / M, n = it - r * M;
@@ -276,7 +334,8 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
       }
     }
     __syncthreads();
-    lds_fft_chunked<T, emax_of<T>(), false>(buf, planM, nlines, H1p, 1, true, twN1, 2);
+    fft_lines<T, emax<T>(), false>(*planM, nlines, true, twl, 2, lds, lds, lds);
+    __syncthreads();
     // R2C merge: X[k] = (A - i w^-k B)/2 with A = Z[k] + conj(Z[M-k]), B = Z[k] - conj(Z[M-k])
     const T hs = (T)(0.5 * xg.invN);
     for (int it = threadIdx.x; it < nlines * kh; it += kThreads) {
@@ -289,8 +348,8 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
       } else {
         const int k1 = kk, k2 = M - kk;
         const cpx<T> a = Z[k1], b = Z[k2];
-        const cpx<T> x1 = scale((a + conjg(b)) - mul_i(twN1[k1] * (a - conjg(b))), hs);
-        if (k2 != k1) Z[k2] = scale((b + conjg(a)) - mul_i(twN1[k2] * (b - conjg(a))), hs);
+        const cpx<T> x1 = scale((a + conjg(b)) - mul_i(twl[k1] * (a - conjg(b))), hs);
+        if (k2 != k1) Z[k2] = scale((b + conjg(a)) - mul_i(twl[k2] * (b - conjg(a))), hs);
         Z[k1] = x1;
       }
     }
@@ -304,104 +363,177 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
   }
   block_sum<6>(acc, red);
   if (threadIdx.x == 0) {
-    double* p = d.part_sig + (long long)blockIdx.x * 6;
+    double* p = d.part_sig + (long long)(xg.half >= 0 ? 2 * tile + half : tile) * 6;
 #pragma unroll
     for (int c = 0; c < 6; ++c) p[c] = acc[c];
   }
 }
 
 // ----------------------------------------------------------------------------
-// P5: equilibrium residual, Green operator, update (eqs. Green_tensor, basic_scheme_dep_2)
+// P5: residual r = sigma^T1.conj(D~) + sigma^T2.conj(D~2) (eq. Equilibrium_Q_div_bis),
+// formed before the forward z transform as R(l3) = A(l3) + B(l3 + 1) with
+// A = sigma.conj(alpha), B = sigma.conj(beta); then the transform of its 3 comps,
+// the Green operator in FP64 (eq. Green_tensor) and the update (eq. basic_scheme_dep_2).
 // MODE 0: u[1-parity] = u[parity] - Omega r
 // MODE 1: FP64 sweep of the anchor: store r in r32, no update
 // MODE 2: refinement inner step: r += r32, u[1-parity] = u[parity] - Omega r
 // ----------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void sig_dot(const cpx<T> (&s)[6], const cpx<double>* c, cpx<double>* out) {
+  // out_i = sum_j s_ij c_j, comps (11,22,33,23,13,12)
+  const cpx<double> s0 = to64(s[0]), s1 = to64(s[1]), s2 = to64(s[2]);
+  const cpx<double> s3 = to64(s[3]), s4 = to64(s[4]), s5 = to64(s[5]);
+  out[0] = s0 * c[0] + s5 * c[1] + s4 * c[2];
+  out[1] = s5 * c[0] + s1 * c[1] + s3 * c[2];
+  out[2] = s4 * c[0] + s3 * c[1] + s2 * c[2];
+}
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads) void k_contract(const Desc* __restrict__ descs,
-                                                       const int* __restrict__ active, int parity,
-                                                       Geo g, const cpx<double>* __restrict__ tw1,
-                                                       const cpx<double>* __restrict__ tw2,
-                                                       const cpx<double>* __restrict__ tw3) {
+__global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ descs, const int* __restrict__ active,
+                                                   ZGeo zg, const Plan* __restrict__ plan3, const cpx<T>* __restrict__ tw3T,
+                                                   const cpx<double>* __restrict__ tw1,
+                                                   const cpx<double>* __restrict__ tw2,
+                                                   const cpx<double>* __restrict__ tw3) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[4];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
-  const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-  double part[1] = {0.0};
-  if (idx < g.S) {
-    const int h2 = (int)(idx % g.N2);
-    const int h3 = (int)((idx / g.N2) % g.N3);
-    const int h1 = (int)(idx / ((long long)g.N2 * g.N3));
-    cpx<double> D1[3], D2[3];
-    symbols(tw1[h1], tw2[h2], tw3[h3], D1, D2);
-    cpx<double> s1[6], s2[6];
+  const int TX = zg.TX, N2 = zg.N2, N3 = zg.N3;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int h1 = tile / zg.tiles;
+  const int h2_0 = (tile % zg.tiles) * TX;
+  const int lines = 3 * TX;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* twl = buf + lines * N3;
+  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
+  const long long plane = (long long)h1 * N3 * N2 + h2_0;
+  const LdsAcc<T> lds{buf, 1, lines};
+  const cpx<T>* sp = reinterpret_cast<const cpx<T>*>(d.spec) + plane;
+  const cpx<double> t1 = tw1[h1];
+  // phase A: each thread walks a run of l3 values of one column downwards, so that
+  // R(l) = A(l) + B(l+1) needs one extra row of loads per run, not one per element
+  const int ne = TX * N3;
+  const int m = (ne + kThreads - 1) / kThreads;  // run length
+  const int nruns = (N3 + m - 1) / m;
+  for (int wk = threadIdx.x; wk < TX * nruns; wk += kThreads) {
+    const int col = wk % TX, run = wk / TX;
+    {
+      cpx<double> a1[3], b1[3], a2[3], b2[3];
+      affine_symbols(t1, tw2[h2_0 + col], a1, b1, a2, b2);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      s1[c] = to64(ld<T>(d.spec, c * g.S + idx));
-      s2[c] = to64(ld<T>(d.spec, (6 + c) * g.S + idx));
-    }
-    // (sigma . conj(D))_i with sigma_ij from comps (11,22,33,23,13,12)
-    const cpx<double> c1[3] = {conjg(D1[0]), conjg(D1[1]), conjg(D1[2])};
-    const cpx<double> c2[3] = {conjg(D2[0]), conjg(D2[1]), conjg(D2[2])};
-    cpx<double> r[3];
-    r[0] = s1[0] * c1[0] + s1[5] * c1[1] + s1[4] * c1[2] + s2[0] * c2[0] + s2[5] * c2[1] + s2[4] * c2[2];
-    r[1] = s1[5] * c1[0] + s1[1] * c1[1] + s1[3] * c1[2] + s2[5] * c2[0] + s2[1] * c2[1] + s2[3] * c2[2];
-    r[2] = s1[4] * c1[0] + s1[3] * c1[1] + s1[2] * c1[2] + s2[4] * c2[0] + s2[3] * c2[1] + s2[2] * c2[2];
-    if (MODE == 2) {
+      for (int c = 0; c < 3; ++c) {
+        a1[c] = conjg(a1[c]); b1[c] = conjg(b1[c]); a2[c] = conjg(a2[c]); b2[c] = conjg(b2[c]);
+      }
+      const int l0 = run * m;
+      const int l1 = min(l0 + m, N3);  // rows l0 .. l1-1 produced, row l1 (mod N3) read
+      cpx<double> Bn[3];
+      {
+        const int l = l1 == N3 ? 0 : l1;
+        const long long o = (long long)l * N2 + col;
+        cpx<T> s1[6], s2[6];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) r[c] = r[c] + to64(ld<float>(d.r32, c * g.S + idx));
-    }
-    const double w = (h1 == 0 || 2 * h1 == g.N1) ? 1.0 : 2.0;
-    part[0] = 0.25 * w * (r[0].x * r[0].x + r[0].y * r[0].y + r[1].x * r[1].x + r[1].y * r[1].y +
-                          r[2].x * r[2].x + r[2].y * r[2].y);
-    if (MODE == 1) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) st<float>(d.r32, c * g.S + idx, fr64<float>(r[c]));
-    } else {
-      // K_il = sum_jk C0_ijkl M_jk,  M_jk = 2 Re(conj(D_j) D_k)
-      double Mjk[3][3];
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) Mjk[j][k] = 2.0 * (D1[j].x * D1[k].x + D1[j].y * D1[k].y);
-      double K[3][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          double a = 0.0;
-#pragma unroll
-          for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) a += d.C0[((i * 3 + j) * 3 + k) * 3 + l] * Mjk[j][k];
-          K[i][l] = a;
+        for (int c = 0; c < 6; ++c) {
+          s1[c] = sp[c * zg.S + o];
+          s2[c] = sp[(6 + c) * zg.S + o];
         }
-      const bool sing = (h1 == 0 && h2 == 0 && h3 == 0) ||
-                        (2 * h1 == g.N1 && 2 * h2 == g.N2 && 2 * h3 == g.N3);
-      // Omega = K^-1 by the adjugate (K symmetric)
-      const double a00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
-      const double a01 = K[0][2] * K[2][1] - K[0][1] * K[2][2];
-      const double a02 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
-      const double a11 = K[0][0] * K[2][2] - K[0][2] * K[2][0];
-      const double a12 = K[0][2] * K[1][0] - K[0][0] * K[1][2];
-      const double a22 = K[0][0] * K[1][1] - K[0][1] * K[1][0];
-      const double det = K[0][0] * a00 + K[0][1] * a01 + K[0][2] * a02;
-      const double inv = sing ? 0.0 : 1.0 / det;
-      const double O[3][3] = {{a00 * inv, a01 * inv, a02 * inv},
-                              {a01 * inv, a11 * inv, a12 * inv},
-                              {a02 * inv, a12 * inv, a22 * inv}};
-      const void* uin = d.u[parity];
-      void* uout = d.u[1 - parity];
+        cpx<double> y1[3], y2[3];
+        sig_dot(s1, b1, y1);
+        sig_dot(s2, b2, y2);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const cpx<double> dw = {O[i][0] * r[0].x + O[i][1] * r[1].x + O[i][2] * r[2].x,
-                                O[i][0] * r[0].y + O[i][1] * r[1].y + O[i][2] * r[2].y};
-        const cpx<double> un = to64(ld<T>(uin, i * g.S + idx)) - dw;
-        st<T>(uout, i * g.S + idx, fr64<T>(un));
+        for (int c = 0; c < 3; ++c) Bn[c] = y1[c] + y2[c];
+      }
+#pragma unroll 1
+      for (int l = l1 - 1; l >= l0; --l) {
+        {
+          const long long o = (long long)l * N2 + col;
+          cpx<T> s1[6], s2[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            s1[c] = sp[c * zg.S + o];
+            s2[c] = sp[(6 + c) * zg.S + o];
+          }
+          cpx<double> x1[3], x2[3], y1[3], y2[3];
+          sig_dot(s1, a1, x1);
+          sig_dot(s2, a2, x2);
+          sig_dot(s1, b1, y1);
+          sig_dot(s2, b2, y2);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            lds.put(c * TX + col, l, fr64<T>(x1[c] + x2[c] + Bn[c]));
+            Bn[c] = y1[c] + y2[c];
+          }
+        }
       }
     }
   }
+  __syncthreads();
+  fft_lines<T, emax<T>(), false>(*plan3, lines, false, twl, 1, lds, lds, lds);
+  __syncthreads();
+  // phase C: Green operator and update at q = (h1, h2, h3)
+  double part[1] = {0.0};
+  const double w = (h1 == 0 || 2 * h1 == zg.N1) ? 1.0 : 2.0;
+  for (int e = threadIdx.x; e < ne; e += kThreads) {
+    const int col = e % TX, h3 = e / TX;
+    const int h2 = h2_0 + col;
+    const long long o = (long long)h3 * N2 + col;
+    cpx<double> r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = to64(lds.get(c * TX + col, h3));
+    if (MODE == 2) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c] = r[c] + to64(reinterpret_cast<const cpx<float>*>(d.r32)[c * zg.S + plane + o]);
+    }
+    part[0] += 0.25 * w * (r[0].x * r[0].x + r[0].y * r[0].y + r[1].x * r[1].x + r[1].y * r[1].y +
+                           r[2].x * r[2].x + r[2].y * r[2].y);
+    if (MODE == 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) reinterpret_cast<cpx<float>*>(d.r32)[c * zg.S + plane + o] = fr64<float>(r[c]);
+      continue;
+    }
+    cpx<double> D1[3], D2[3];
+    symbols(t1, tw2[h2], tw3[h3], D1, D2);
+    // K_il = sum_jk C0_ijkl M_jk,  M_jk = 2 Re(conj(D_j) D_k)
+    double Mjk[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Mjk[j][k] = 2.0 * (D1[j].x * D1[k].x + D1[j].y * D1[k].y);
+    double K[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) acc += d.C0[((i * 3 + j) * 3 + k) * 3 + l] * Mjk[j][k];
+        K[i][l] = acc;
+      }
+    const bool sing = (h1 == 0 && h2 == 0 && h3 == 0) || (2 * h1 == zg.N1 && 2 * h2 == N2 && 2 * h3 == N3);
+    // Omega = K^-1 by the adjugate (K symmetric)
+    const double a00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
+    const double a01 = K[0][2] * K[2][1] - K[0][1] * K[2][2];
+    const double a02 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
+    const double a11 = K[0][0] * K[2][2] - K[0][2] * K[2][0];
+    const double a12 = K[0][2] * K[1][0] - K[0][0] * K[1][2];
+    const double a22 = K[0][0] * K[1][1] - K[0][1] * K[1][0];
+    const double det = K[0][0] * a00 + K[0][1] * a01 + K[0][2] * a02;
+    const double inv = sing ? 0.0 : 1.0 / det;
+    const double O[3][3] = {{a00 * inv, a01 * inv, a02 * inv},
+                            {a01 * inv, a11 * inv, a12 * inv},
+                            {a02 * inv, a12 * inv, a22 * inv}};
+    const cpx<T>* uin = reinterpret_cast<const cpx<T>*>(d.u[zg.parity]) + plane;
+    cpx<T>* uout = reinterpret_cast<cpx<T>*>(d.u[1 - zg.parity]) + plane;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const cpx<double> dw = {O[i][0] * r[0].x + O[i][1] * r[1].x + O[i][2] * r[2].x,
+                              O[i][0] * r[0].y + O[i][1] * r[1].y + O[i][2] * r[2].y};
+      uout[i * zg.S + o] = fr64<T>(to64(uin[i * zg.S + o]) - dw);
+    }
+  }
   block_sum<1>(part, red);
-  if (threadIdx.x == 0) d.part_res[blockIdx.x] = part[0];
+  if (threadIdx.x == 0) d.part_res[tile] = part[0];
 }
 
 // ----------------------------------------------------------------------------
@@ -507,56 +639,52 @@ __global__ __launch_bounds__(kThreads) void k_zero(const Desc* __restrict__ desc
 // launch wrappers
 // ----------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_expand(const Desc* descs, const int* active, int nact, int parity, int src,
-                         const Geo& g, const void* tw1, const void* tw2, const void* tw3,
-                         hipStream_t s) {
-  dim3 grid((unsigned)((g.S + kThreads - 1) / kThreads), nact);
-  hipLaunchKernelGGL(k_expand<T>, grid, dim3(kThreads), 0, s, descs, active, parity, src, g,
-                     (const cpx<double>*)tw1, (const cpx<double>*)tw2, (const cpx<double>*)tw3);
+hipError_t launch_zexp(const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
+                       const void* tw3T, const void* tw1, const void* tw2, hipStream_t s) {
+  const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
+  dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
+  hipLaunchKernelGGL(k_zexp<T>, grid, dim3(kThreads), shm, s, descs, active, zg, plan3, (const cpx<T>*)tw3T,
+                     (const cpx<double>*)tw1, (const cpx<double>*)tw2);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_lines(const Desc* descs, const int* active, int nact, const LinesGeo& lg,
-                        const Plan& plan, const void* tw, bool inv, hipStream_t s) {
-  unsigned nblk;
-  if (lg.mode == 0) nblk = (unsigned)((lg.nlines + lg.TX - 1) / lg.TX);
-  else nblk = (unsigned)((long long)lg.tiles_per_plane * (lg.nlines));  // nlines = planes for mode 1
-  const size_t shm = (size_t)lg.TX * lg.L * sizeof(cpx<T>);
-  dim3 grid(nblk, nact);
+hipError_t launch_yline(const Desc* descs, const int* active, int nact, const YGeo& yg, const Plan* plan2,
+                        const void* tw2T, bool inv, hipStream_t s) {
+  const size_t shm = ((size_t)yg.TX * yg.N2 + yg.N2) * sizeof(cpx<T>);
+  dim3 grid((unsigned)((yg.nlines + yg.TX - 1) / yg.TX), nact);
   if (inv)
-    hipLaunchKernelGGL((k_lines<T, true>), grid, dim3(kThreads), shm, s, descs, active, lg, plan,
-                       (const cpx<T>*)tw);
+    hipLaunchKernelGGL((k_yline<T, true>), grid, dim3(kThreads), shm, s, descs, active, yg, plan2, (const cpx<T>*)tw2T);
   else
-    hipLaunchKernelGGL((k_lines<T, false>), grid, dim3(kThreads), shm, s, descs, active, lg, plan,
-                       (const cpx<T>*)tw);
+    hipLaunchKernelGGL((k_yline<T, false>), grid, dim3(kThreads), shm, s, descs, active, yg, plan2, (const cpx<T>*)tw2T);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_xpass(const Desc* descs, const int* active, int nact, const XGeo& xg,
-                        const Plan& planM, const void* twN1, hipStream_t s) {
-  const size_t shm = (size_t)6 * xg.TY * xg.H1p * sizeof(cpx<T>);
-  dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY)), nact);
+                        const Plan* planM, const void* twN1, hipStream_t s) {
+  const size_t shm = ((size_t)6 * xg.TY * xg.H1p + xg.N1) * sizeof(cpx<T>);
+  dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY) * (xg.half >= 0 ? 1 : 2)), nact);
   hipLaunchKernelGGL(k_xpass<T>, grid, dim3(kThreads), shm, s, descs, active, xg, planM,
                      (const cpx<T>*)twN1);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_contract(int mode, const Desc* descs, const int* active, int nact, int parity,
-                           const Geo& g, const void* tw1, const void* tw2, const void* tw3,
-                           hipStream_t s) {
-  dim3 grid((unsigned)((g.S + kThreads - 1) / kThreads), nact);
-  const cpx<double>* a = (const cpx<double>*)tw1;
-  const cpx<double>* b = (const cpx<double>*)tw2;
-  const cpx<double>* c = (const cpx<double>*)tw3;
+hipError_t launch_zcon(int mode, const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
+                       const void* tw3T, const void* tw1, const void* tw2, const void* tw3, hipStream_t s) {
+  const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
+  dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
+  const cpx<T>* a = (const cpx<T>*)tw3T;
+  const cpx<double>* b = (const cpx<double>*)tw1;
+  const cpx<double>* c = (const cpx<double>*)tw2;
+  const cpx<double>* e = (const cpx<double>*)tw3;
   if (mode == 0)
-    hipLaunchKernelGGL((k_contract<T, 0>), grid, dim3(kThreads), 0, s, descs, active, parity, g, a, b, c);
+    hipLaunchKernelGGL((k_zcon<T, 0>), grid, dim3(kThreads), shm, s, descs, active, zg, plan3, a, b, c, e);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_contract<T, 1>), grid, dim3(kThreads), 0, s, descs, active, parity, g, a, b, c);
+    hipLaunchKernelGGL((k_zcon<T, 1>), grid, dim3(kThreads), shm, s, descs, active, zg, plan3, a, b, c, e);
   else
-    hipLaunchKernelGGL((k_contract<T, 2>), grid, dim3(kThreads), 0, s, descs, active, parity, g, a, b, c);
+    hipLaunchKernelGGL((k_zcon<T, 2>), grid, dim3(kThreads), shm, s, descs, active, zg, plan3, a, b, c, e);
   return hipGetLastError();
 }
 
@@ -580,13 +708,13 @@ hipError_t launch_zero(const Desc* descs, const int* active, int nact, int what,
   return hipGetLastError();
 }
 
-template hipError_t launch_expand<double>(const Desc*, const int*, int, int, int, const Geo&, const void*, const void*, const void*, hipStream_t);
-template hipError_t launch_expand<float>(const Desc*, const int*, int, int, int, const Geo&, const void*, const void*, const void*, hipStream_t);
-template hipError_t launch_lines<double>(const Desc*, const int*, int, const LinesGeo&, const Plan&, const void*, bool, hipStream_t);
-template hipError_t launch_lines<float>(const Desc*, const int*, int, const LinesGeo&, const Plan&, const void*, bool, hipStream_t);
-template hipError_t launch_xpass<double>(const Desc*, const int*, int, const XGeo&, const Plan&, const void*, hipStream_t);
-template hipError_t launch_xpass<float>(const Desc*, const int*, int, const XGeo&, const Plan&, const void*, hipStream_t);
-template hipError_t launch_contract<double>(int, const Desc*, const int*, int, int, const Geo&, const void*, const void*, const void*, hipStream_t);
-template hipError_t launch_contract<float>(int, const Desc*, const int*, int, int, const Geo&, const void*, const void*, const void*, hipStream_t);
+template hipError_t launch_zexp<double>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, hipStream_t);
+template hipError_t launch_zexp<float>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, hipStream_t);
+template hipError_t launch_yline<double>(const Desc*, const int*, int, const YGeo&, const Plan*, const void*, bool, hipStream_t);
+template hipError_t launch_yline<float>(const Desc*, const int*, int, const YGeo&, const Plan*, const void*, bool, hipStream_t);
+template hipError_t launch_xpass<double>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xpass<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_zcon<double>(int, const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
+template hipError_t launch_zcon<float>(int, const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
 
 }  // namespace hz

@@ -89,6 +89,12 @@ def check_pair(shape, g, r, ref, K, fields=True):
     ((2, 4, 6), 2, 4, "aniso", False, 5),        # degenerate N1 = 2
     ((32, 48, 40), 2, 5, "iso", False, 4),       # several tiles in every pass, ragged y tile
     ((40, 30, 18), 3, 6, "aniso", False, 3),
+    ((128, 16, 16), 2, 7, "iso", False, 3),      # x tile larger than one load batch; radix 16 x 4
+    ((64, 32, 32), 2, 8, "aniso", False, 3),     # radix 16 x 2 along x
+    ((256, 8, 8), 2, 9, "iso", False, 2),        # radix 16 x 8 along x, narrow y/z
+    ((16, 256, 8), 2, 10, "iso", False, 2),      # radix 16 x 16 along y
+    ((16, 8, 256), 2, 11, "iso", False, 2),      # radix 16 x 16 along z
+    ((96, 48, 40), 2, 12, "aniso", True, 3),     # radix 3 and 5 at medium size, voids
 ])
 def test_fp64_iterates_match_oracle(shape, n_phases, seed, kind, voids, K):
     _say(f"case shape={shape} seed={seed} kind={kind} voids={voids}")
