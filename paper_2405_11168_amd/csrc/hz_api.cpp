@@ -61,12 +61,24 @@ bool factor_ok(int n) {
   return n == 1;
 }
 
+// r = (1 + 2^-20) / d rounded up to float: floor(a / d) = int(float(a) * r) for a < 2^19
+float recip(int d) {
+  const double x = (1.0 + std::ldexp(1.0, -20)) / (double)d;
+  float f = (float)x;
+  if ((double)f < x) f = std::nextafter(f, 2.0f * f + 1.0f);
+  return f;
+}
+
 Plan make_plan(int L) {
   Plan p{};
   p.L = L;
   p.np = 0;
   int n = L;
-  auto push = [&](int r) { p.radix[p.np++] = r; n /= r; };
+  auto push = [&](int r) {
+    if (p.np >= kMaxPasses) fail(HZ_EINVAL, "too many radix passes");
+    p.radix[p.np++] = r;
+    n /= r;
+  };
   while (n % 16 == 0) push(16);
   while (n % 8 == 0) push(8);
   while (n % 4 == 0) push(4);
@@ -74,7 +86,13 @@ Plan make_plan(int L) {
   while (n % 7 == 0) push(7);
   while (n % 5 == 0) push(5);
   while (n % 3 == 0) push(3);
-  if (n != 1 || p.np > kMaxPasses) fail(HZ_EINVAL, "transform length " + std::to_string(L) + " not supported");
+  if (n != 1) fail(HZ_EINVAL, "transform length " + std::to_string(L) + " not supported");
+  int ns = 1;
+  for (int s = 0; s < p.np; ++s) {
+    p.rLR[s] = recip(L / p.radix[s]);
+    p.rNs[s] = recip(ns);
+    ns *= p.radix[s];
+  }
   return p;
 }
 
@@ -110,6 +128,9 @@ struct hz_grid_s {
   hipStream_t stream = nullptr;
   int prec = -1;
   int cap = 0;
+  int iso = 0;
+  int c0_iso = 0;
+  double lam0 = 0, mu0 = 0;
   struct Off {
     size_t tw64[3], tw32[3], plans, C64, C32, phase, descs, active, status, status2, part_sig, part_res, trace, fields;
     std::vector<size_t> spec, u0, u1, u64, r32;
@@ -156,7 +177,7 @@ void compute_tiling(hz_grid g) {
     if (ty < 1 || G.N2 > tile || (ty * G.N2 + G.N2) * csz > kLdsBytes) fail(HZ_EINVAL, "N2 too large");
     g->TXy[d] = ty;
     // x kernel: 6 comps x TY rows x (N1/2+1) in LDS (+ N1 twiddles), TY | N2
-    const int hp = G.H1 | 1;  // odd pitch spreads rows across LDS banks
+    const int hp = (G.N1 / 2) | 1;  // lines hold M = N1/2 values; odd pitch spreads rows over banks
     int tyx = std::min(16, G.N2);
     while (tyx > 1 && ((6 * tyx * hp + G.N1) * csz > kLdsBytes || 6 * tyx * (G.N1 / 2) > tile || G.N2 % tyx)) --tyx;
     if ((6 * tyx * hp + G.N1) * csz > kLdsBytes || 6 * tyx * (G.N1 / 2) > tile) fail(HZ_EINVAL, "N1 too large");
@@ -176,8 +197,8 @@ void layout(hz_grid g, int prec, int nl, hz_grid_s::Off& o) {
   for (int a = 0; a < 3; ++a) o.tw32[a] = take((size_t)Ns[a] * 8);
   o.plans = take(4 * sizeof(Plan));  // N1, N2, N3, N1/2
   const int np = std::max(1, g->n_phases);
-  o.C64 = take((size_t)np * 36 * 8);
-  o.C32 = take((size_t)np * 36 * 4);
+  o.C64 = take((size_t)np * 24 * 8);
+  o.C32 = take((size_t)np * 24 * 4);
   o.phase = take((size_t)G.N * 2);
   o.descs = take((size_t)nl * sizeof(Desc) * 2);
   o.active = take((size_t)nl * 4);
@@ -208,6 +229,8 @@ void layout(hz_grid g, int prec, int nl, hz_grid_s::Off& o) {
   o.total = p;
 }
 
+bool isotropic(const double* C, double& lam, double& mu);
+
 void upload_tables(hz_grid g) {
   const Geo& G = g->geo;
   const int Ns[3] = {G.N1, G.N2, G.N3};
@@ -227,12 +250,48 @@ void upload_tables(hz_grid g) {
   }
   const Plan plans[4] = {g->plan1, g->plan2, g->plan3, g->planM};
   hip_check(hipMemcpy(g->ws + g->off.plans, plans, sizeof(plans), hipMemcpyHostToDevice), "upload plans");
-  std::vector<float> c32(g->C.size());
-  for (size_t i = 0; i < c32.size(); ++i) c32[i] = (float)g->C[i];
-  hip_check(hipMemcpy(g->ws + g->off.C64, g->C.data(), g->C.size() * 8, hipMemcpyHostToDevice), "upload C");
+  // per-phase tables: (lambda, mu) when every phase is isotropic, else the Voigt upper triangle
+  const int np = g->n_phases;
+  std::vector<double> c64((size_t)np * 24, 0.0);
+  g->iso = 1;
+  for (int p = 0; p < np; ++p) {
+    double lam, mu;
+    if (!isotropic(g->C.data() + 36 * p, lam, mu)) g->iso = 0;
+  }
+  for (int p = 0; p < np; ++p) {
+    const double* C = g->C.data() + 36 * p;
+    if (g->iso) {
+      isotropic(C, c64[2 * p], c64[2 * p + 1]);
+    } else {
+      int n = 0;
+      for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) c64[(size_t)p * 24 + n++] = C[i * 6 + j];
+    }
+  }
+  std::vector<float> c32(c64.size());
+  for (size_t i = 0; i < c32.size(); ++i) c32[i] = (float)c64[i];
+  hip_check(hipMemcpy(g->ws + g->off.C64, c64.data(), c64.size() * 8, hipMemcpyHostToDevice), "upload C");
   hip_check(hipMemcpy(g->ws + g->off.C32, c32.data(), c32.size() * 4, hipMemcpyHostToDevice), "upload C");
   hip_check(hipMemcpy(g->ws + g->off.phase, g->phase.data(), g->phase.size() * 2, hipMemcpyHostToDevice),
             "upload phase map");
+}
+
+// isotropic engineering Voigt stiffness: C11=C22=C33 = lam + 2 mu, C12=C13=C23 = lam,
+// C44=C55=C66 = mu, every other entry zero (relative tolerance 1e-12)
+bool isotropic(const double* C, double& lam, double& mu) {
+  lam = C[1];
+  mu = C[21];
+  double scale = 0;
+  for (int i = 0; i < 36; ++i) scale = std::max(scale, std::fabs(C[i]));
+  const double tol = 1e-12 * scale;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      double e = 0;
+      if (i < 3 && j < 3) e = (i == j) ? lam + 2 * mu : lam;
+      else if (i == j) e = mu;
+      if (std::fabs(C[i * 6 + j] - e) > tol) return false;
+    }
+  return true;
 }
 
 void voigt_to_tensor(const double* C, double* T) {
@@ -371,7 +430,8 @@ void pipeline_front(Ctx& c, int parity, int src) {
   const int d = sizeof(T) == 8;
   const size_t* tw = d ? g->off.tw64 : g->off.tw32;
   Launcher L{g};
-  ZGeo zg{G.N1, G.N2, G.N3, G.H1, g->TXz[d], G.N2 / g->TXz[d], G.S, parity, src};
+  ZGeo zg{G.N1, G.N2, G.N3, G.H1, g->TXz[d], G.N2 / g->TXz[d], recip(g->TXz[d]), recip(3 * g->TXz[d]),
+          recip(G.N2 / g->TXz[d]), G.S, parity, src};
   L.begin(K_ZEXP, d);
   L.end(launch_zexp<T>(c.dd, c.act, c.nact, zg, P<Plan>(g, g->off.plans) + 2, g->ws + tw[2], g->ws + g->off.tw64[0],
                        g->ws + g->off.tw64[1], g->stream),
@@ -390,7 +450,9 @@ void pipeline_x(Ctx& c, int fields) {
   Launcher L{g};
   // with fields, T1 writes and T2 then adds its half of the averages: two launches
   for (int h = fields ? 0 : -1; h < (fields ? 2 : 0); ++h) {
-    XGeo xg{G.N1, G.N2, G.N3, G.H1, g->H1p[d], g->TYx[d], G.N1 / 2, G.S, 1.0 / (double)G.N, fields, h};
+    const int M = G.N1 / 2;
+    XGeo xg{G.N1, G.N2, G.N3, G.H1, g->H1p[d], g->TYx[d], M, recip(g->TYx[d]), recip(M / 2 + 1), recip(M),
+            G.S, 1.0 / (double)G.N, fields, h};
     L.begin(K_XPASS, d);
     L.end(launch_xpass<T>(c.dd, c.act, c.nact, xg, P<Plan>(g, g->off.plans) + 3, g->ws + tw[0], g->stream), "x pass");
   }
@@ -407,7 +469,8 @@ void pipeline_back(Ctx& c, int parity, int mode) {
   YGeo yg{G.N2, g->TXy[d], (long long)12 * G.H1 * G.N3};
   L.begin(K_YFWD, d);
   L.end(launch_yline<T>(c.dd, c.act, c.nact, yg, P<Plan>(g, g->off.plans) + 1, g->ws + tw[1], false, g->stream), "y forward");
-  ZGeo zg{G.N1, G.N2, G.N3, G.H1, g->TXz[d], G.N2 / g->TXz[d], G.S, parity, 0};
+  ZGeo zg{G.N1, G.N2, G.N3, G.H1, g->TXz[d], G.N2 / g->TXz[d], recip(g->TXz[d]), recip(3 * g->TXz[d]),
+          recip(G.N2 / g->TXz[d]), G.S, parity, 0};
   L.begin(K_ZCON, d);
   L.end(launch_zcon<T>(mode, c.dd, c.act, c.nact, zg, P<Plan>(g, g->off.plans) + 2, g->ws + tw[2], g->ws + g->off.tw64[0],
                        g->ws + g->off.tw64[1], g->ws + g->off.tw64[2], g->stream),
@@ -449,6 +512,10 @@ Desc base_desc(hz_grid g, int b, const double* E, const double* C0t, double tol,
   d.trace_len = inner ? 0 : kTraceCap;
   for (int c = 0; c < 6; ++c) d.Ebar[c] = inner ? 0.0 : E[c];
   std::memcpy(d.C0, C0t, sizeof(d.C0));
+  d.iso = g->iso;
+  d.c0_iso = g->c0_iso;
+  d.lam0 = g->lam0;
+  d.mu0 = g->mu0;
   d.tol = tol;
   d.max_iters = max_iters;
   d.fixed_iters = fixed;
@@ -911,6 +978,7 @@ int hz_solve(hz_grid g, int32_t n_loads, const double* E, const hz_opts* o, doub
       if (!(e > 0)) fail(HZ_ENOTSPD, "reference medium is not positive definite");
   }
   voigt_to_tensor(C0, C0t);
+  g->c0_iso = isotropic(C0, g->lam0, g->mu0) ? 1 : 0;
   g->last_loads = n_loads;
   g->last_prec = o->precision;
   if (o->precision == HZ_FP64) return solve_fp64(g, n_loads, E, *o, C0t, sigma_mean, eps_out, sig_out, info);

@@ -202,12 +202,16 @@ struct GblAcc {
   __device__ __forceinline__ void put(int t, int j, cpx<T> v) const { p[at(t, j)] = v; }
 };
 
-__device__ __forceinline__ void line_map(int b, int lines, int LR, bool jfast, int& t, int& j) {
+// floor(a / d) for 0 <= a < 2^19 given r = (1 + 2^-20)/d rounded up (see Plan)
+__device__ __forceinline__ int fdiv(int a, float r) { return (int)((float)a * r); }
+
+__device__ __forceinline__ void line_map(int b, int lines, int LR, float rLR, float rlines, bool jfast, int& t,
+                                         int& j) {
   if (jfast) {
-    t = b / LR;
+    t = fdiv(b, rLR);
     j = b - t * LR;
   } else {
-    j = b / lines;
+    j = fdiv(b, rlines);
     t = b - j * lines;
   }
 }
@@ -217,7 +221,8 @@ __device__ __forceinline__ void line_map(int b, int lines, int LR, bool jfast, i
 // `inplace` puts a barrier between reading src and writing dst (same LDS buffer).
 template <typename T, int R, int BMAX, bool INV, class SRC, class DST>
 __device__ __forceinline__ void pass_gen(int L, int Ns, int lines, bool jfast, const cpx<T>* __restrict__ tw,
-                                         int tstride, const SRC& src, const DST& dst, bool inplace) {
+                                         int tstride, const SRC& src, const DST& dst, bool inplace, float rLR,
+                                         float rNs, float rlines) {
   const int LR = L / R;
   const int nb = lines * LR;
   const int tid = threadIdx.x;
@@ -229,7 +234,7 @@ __device__ __forceinline__ void pass_gen(int L, int Ns, int lines, bool jfast, c
     const int b = tid + i * kThreads;
     if (b < nb) {
       int t, j;
-      line_map(b, lines, LR, jfast, t, j);
+      line_map(b, lines, LR, rLR, rlines, jfast, t, j);
 #pragma unroll
       for (int m = 0; m < R; ++m) v[i][m] = src.get(t, j + m * LR);
     }
@@ -240,8 +245,8 @@ __device__ __forceinline__ void pass_gen(int L, int Ns, int lines, bool jfast, c
     if (b < nb) {
       if (Ns > 1) {
         int t, j;
-        line_map(b, lines, LR, jfast, t, j);
-        const int k = j % Ns;
+        line_map(b, lines, LR, rLR, rlines, jfast, t, j);
+        const int k = j - fdiv(j, rNs) * Ns;
 #pragma unroll
         for (int m = 1; m < R; ++m) {
           cpx<T> w = tw[m * k * tws];
@@ -258,9 +263,10 @@ __device__ __forceinline__ void pass_gen(int L, int Ns, int lines, bool jfast, c
     const int b = tid + i * kThreads;
     if (b < nb) {
       int t, j;
-      line_map(b, lines, LR, jfast, t, j);
-      const int k = j % Ns;
-      const int base = (j / Ns) * span + k;
+      line_map(b, lines, LR, rLR, rlines, jfast, t, j);
+      const int q = fdiv(j, rNs);
+      const int k = j - q * Ns;
+      const int base = q * span + k;
 #pragma unroll
       for (int m = 0; m < R; ++m) dst.put(t, base + m * Ns, v[i][m]);
     }
@@ -272,16 +278,24 @@ constexpr int bmax() { return (EMAX + R - 1) / R; }
 
 template <typename T, int EMAX, bool INV, class SRC, class DST>
 __device__ __forceinline__ void pass_any(int R, int L, int Ns, int lines, bool jfast, const cpx<T>* __restrict__ tw,
-                                         int tstride, const SRC& src, const DST& dst, bool inplace) {
+                                         int tstride, const SRC& src, const DST& dst, bool inplace, float rLR,
+                                         float rNs, float rl) {
+#define HZ_CASE(RR)                                                                                      \
+  case RR:                                                                                               \
+    pass_gen<T, RR, bmax<EMAX, RR>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace, rLR, rNs, rl); \
+    break;
   switch (R) {
-    case 16: pass_gen<T, 16, bmax<EMAX, 16>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
-    case 8: pass_gen<T, 8, bmax<EMAX, 8>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
-    case 4: pass_gen<T, 4, bmax<EMAX, 4>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
-    case 2: pass_gen<T, 2, bmax<EMAX, 2>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
-    case 7: pass_gen<T, 7, bmax<EMAX, 7>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
-    case 5: pass_gen<T, 5, bmax<EMAX, 5>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
-    default: pass_gen<T, 3, bmax<EMAX, 3>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace); break;
+    HZ_CASE(16)
+    HZ_CASE(8)
+    HZ_CASE(4)
+    HZ_CASE(2)
+    HZ_CASE(7)
+    HZ_CASE(5)
+    default:
+      pass_gen<T, 3, bmax<EMAX, 3>(), INV>(L, Ns, lines, jfast, tw, tstride, src, dst, inplace, rLR, rNs, rl);
+      break;
   }
+#undef HZ_CASE
 }
 
 // Whole transform of `lines` lines (lines * L <= EMAX * kThreads), unnormalised.
@@ -291,25 +305,29 @@ __device__ __forceinline__ void pass_any(int R, int L, int Ns, int lines, bool j
 // is LDS the caller synchronises before reading it; when src is LDS the caller
 // synchronised after filling it.
 template <typename T, int EMAX, bool INV, class SRC, class DST>
-__device__ __forceinline__ void fft_lines(const Plan& plan, int lines, bool jfast, const cpx<T>* __restrict__ tw, int tstride,
-                          const LdsAcc<T>& lds, const SRC& src, const DST& dst) {
+__device__ __forceinline__ void fft_lines(const Plan& plan, int lines, float rlines, bool jfast,
+                                          const cpx<T>* __restrict__ tw, int tstride, const LdsAcc<T>& lds,
+                                          const SRC& src, const DST& dst) {
   const int np = plan.np, L = plan.L;
   if (np == 0) {  // L == 1: copy
     for (int t = threadIdx.x; t < lines; t += kThreads) dst.put(t, 0, src.get(t, 0));
     return;
   }
   if (np == 1) {
-    pass_any<T, EMAX, INV>(plan.radix[0], L, 1, lines, jfast, tw, tstride, src, dst, SRC::kLds && DST::kLds);
+    pass_any<T, EMAX, INV>(plan.radix[0], L, 1, lines, jfast, tw, tstride, src, dst, SRC::kLds && DST::kLds,
+                           plan.rLR[0], plan.rNs[0], rlines);
     return;
   }
-  pass_any<T, EMAX, INV>(plan.radix[0], L, 1, lines, jfast, tw, tstride, src, lds, SRC::kLds);
+  pass_any<T, EMAX, INV>(plan.radix[0], L, 1, lines, jfast, tw, tstride, src, lds, SRC::kLds, plan.rLR[0],
+                         plan.rNs[0], rlines);
   __syncthreads();
   int Ns = plan.radix[0], s = 1;
-#define HZ_MID(R)                                                                                   \
-  for (; s < np - 1 && plan.radix[s] == R; ++s) {                                                   \
-    pass_gen<T, R, bmax<EMAX, R>(), INV>(L, Ns, lines, jfast, tw, tstride, lds, lds, true);          \
-    __syncthreads();                                                                                \
-    Ns *= R;                                                                                        \
+#define HZ_MID(R)                                                                                         \
+  for (; s < np - 1 && plan.radix[s] == R; ++s) {                                                         \
+    pass_gen<T, R, bmax<EMAX, R>(), INV>(L, Ns, lines, jfast, tw, tstride, lds, lds, true, plan.rLR[s],    \
+                                         plan.rNs[s], rlines);                                            \
+    __syncthreads();                                                                                      \
+    Ns *= R;                                                                                              \
   }
   HZ_MID(16)
   HZ_MID(8)
@@ -319,20 +337,12 @@ __device__ __forceinline__ void fft_lines(const Plan& plan, int lines, bool jfas
   HZ_MID(5)
   HZ_MID(3)
 #undef HZ_MID
-  pass_any<T, EMAX, INV>(plan.radix[np - 1], L, Ns, lines, jfast, tw, tstride, lds, dst, DST::kLds);
+  pass_any<T, EMAX, INV>(plan.radix[np - 1], L, Ns, lines, jfast, tw, tstride, lds, dst, DST::kLds,
+                         plan.rLR[np - 1], plan.rNs[np - 1], rlines);
 }
 
 // elements per thread in one transform call (bounds register use)
 template <typename T>
 constexpr int emax() { return 16; }
-
-// Out-of-line copy for callers that run a transform inside a loop: inlining
-// there lets the compiler hoist every pass variant's index arithmetic out of the
-// loop and keep it live across the whole body.
-template <typename T, int EMAX, bool INV, class SRC, class DST>
-__device__ __noinline__ void fft_lines_call(const Plan* plan, int lines, bool jfast, const cpx<T>* __restrict__ tw,
-                                            int tstride, LdsAcc<T> lds, SRC src, DST dst) {
-  fft_lines<T, EMAX, INV>(*plan, lines, jfast, tw, tstride, lds, src, dst);
-}
 
 }  // namespace hz

@@ -9,10 +9,15 @@ constexpr int kThreads = 256;   // work-group size of every kernel (4 wave64)
 constexpr int kMaxPasses = 16;
 
 // Factorisation of a transform length into Stockham radix passes.
+// Index arithmetic in the kernels divides by these lengths through exact float
+// reciprocals: floor(a / d) = int(float(a) * r) with r = (1 + 2^-20) / d rounded up,
+// exact for 0 <= a < 2^19.
 struct Plan {
   int L;
   int np;
   int radix[kMaxPasses];
+  float rLR[kMaxPasses];   // 1 / (L / radix[s])
+  float rNs[kMaxPasses];   // 1 / (radix[0] * ... * radix[s-1])
 };
 
 // Spectral storage is [comp][h1][h3][h2] with h1 in [0, N1/2] outermost, so the
@@ -32,8 +37,11 @@ struct Desc {
   void* u64;             // refinement: FP64 anchor U (3 comps)
   void* r32;             // refinement: FP64-sweep residual stored in FP32 (3 comps)
   const uint16_t* phase; // [N3][N2][N1]
-  const double* C64;     // [n_phases][36] Voigt
-  const float* C32;      // [n_phases][36] Voigt
+  const double* C64;     // [n_phases][24] Voigt upper triangle (21 used), or (lambda, mu) pairs if iso
+  const float* C32;      // same in FP32
+  int iso;               // 1: every phase isotropic, tables hold (lambda, mu)
+  int c0_iso;            // 1: reference medium isotropic with (lam0, mu0)
+  double lam0, mu0;
   double* part_sig;      // [nbx][6] FP64 partial sums of (sigma^T1 + sigma^T2)/2
   double* part_res;      // [nbq] FP64 partial sums of w |r/2|^2
   double* status;        // [16] device-side state, see St below
@@ -69,6 +77,7 @@ constexpr int kStatusLen = 16;
 // adjacent h2 columns of one h1 plane, all N3 elements, 3 displacement components.
 struct ZGeo {
   int N1, N2, N3, H1, TX, tiles;   // tiles = N2 / TX
+  float rTX, rLines, rTiles;       // reciprocals of TX, 3 TX, tiles
   long long S;
   int parity;
   int src;                          // k_zexp: 0 = u[parity], 1 = FP64 anchor u64
@@ -83,6 +92,7 @@ struct YGeo {
 // fused x pass geometry
 struct XGeo {
   int N1, N2, N3, H1, H1p, TY, M;
+  float rTY, rKH, rM;     // reciprocals of TY, M/2+1, M
   long long S;
   double invN;
   int fields;            // write real-space eps/sigma (T1/T2 averages)

@@ -140,12 +140,12 @@ __global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ desc
   const LdsAcc<T> lds{buf, 1, lines};
   const void* usrc = zg.src == 1 ? d.u64 : d.u[zg.parity];
   const GblAcc<T> src{reinterpret_cast<cpx<T>*>(const_cast<void*>(usrc)) + plane, (int)zg.S, TX, 1, N2};
-  fft_lines<T, emax<T>(), true>(*plan3, lines, false, twl, 1, lds, src, lds);
+  fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, src, lds);
   __syncthreads();
   cpx<T>* out = reinterpret_cast<cpx<T>*>(d.spec) + plane;
   const cpx<double> t1 = tw1[h1];
   for (int e = threadIdx.x; e < TX * N3; e += kThreads) {
-    const int col = e % TX, l3 = e / TX;
+    const int l3 = fdiv(e, zg.rTX), col = e - l3 * TX;
     const int lm = l3 == 0 ? N3 - 1 : l3 - 1;
     cpx<double> a1[3], b1[3], a2[3], b2[3];
     affine_symbols(t1, tw2[h2_0 + col], a1, b1, a2, b2);
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ des
   for (int i = threadIdx.x; i < N2; i += kThreads) twl[i] = tw2T[i];
   const LdsAcc<T> lds{buf, N2, 1};
   const GblAcc<T> g{reinterpret_cast<cpx<T>*>(d.spec) + t0 * N2, N2, 1, 0, 1};
-  fft_lines<T, emax<T>(), INV>(*plan2, lines, true, twl, 1, lds, g, g);
+  fft_lines<T, emax<T>(), INV>(*plan2, lines, 0.f, true, twl, 1, lds, g, g);
 }
 
 // ----------------------------------------------------------------------------
@@ -206,20 +206,47 @@ __global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ des
 // as a complex transform of length M = N1/2, constitutive law per voxel,
 // R2C back (with the 1/N of eq. FT), store.  FP64 partials of <sigma>.
 // ----------------------------------------------------------------------------
+// sigma = C:(Ebar + deps) in tensor comps (11,22,33,23,13,12); C as an engineering
+// Voigt matrix stored as its upper triangle (21 of 24 slots) row by row
 template <typename T>
-__device__ __forceinline__ void constitutive(const T* __restrict__ C, const double* Eb,
-                                             const T (&de)[6], T (&s)[6]) {
+__device__ __forceinline__ void constitutive(const T* __restrict__ Cp, const double* Eb, const T (&de)[6],
+                                             T (&s)[6]) {
   T g[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) g[c] = (T)Eb[c] + de[c];
   g[3] *= (T)2; g[4] *= (T)2; g[5] *= (T)2;  // engineering shears
+  T Cu[24];
+#pragma unroll
+  for (int i = 0; i < 24; i += 2) {
+    const cpx<T> v = reinterpret_cast<const cpx<T>*>(Cp)[i / 2];
+    Cu[i] = v.x;
+    Cu[i + 1] = v.y;
+  }
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     T acc = 0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) acc += C[i * 6 + j] * g[j];
+    for (int j = 0; j < 6; ++j) {
+      const int a = i < j ? i : j, b = i < j ? j : i;
+      acc += Cu[a * 6 - a * (a - 1) / 2 + (b - a)] * g[j];
+    }
     s[i] = acc;
   }
+}
+
+// isotropic phase: sigma = lambda tr(eps) I + 2 mu eps
+template <typename T>
+__device__ __forceinline__ void constitutive_iso(T lam, T mu, const double* Eb, const T (&de)[6], T (&s)[6]) {
+  T e[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) e[c] = (T)Eb[c] + de[c];
+  const T lt = lam * (e[0] + e[1] + e[2]), m2 = (T)2 * mu;
+  s[0] = lt + m2 * e[0];
+  s[1] = lt + m2 * e[1];
+  s[2] = lt + m2 * e[2];
+  s[3] = m2 * e[3];
+  s[4] = m2 * e[4];
+  s[5] = m2 * e[5];
 }
 
 template <typename T>
@@ -237,135 +264,129 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
   const int rt = xg.half >= 0 ? tile : (tile >> 1);
   const int l3 = rt / tiles2;
   const int l2_0 = (rt % tiles2) * xg.TY;
-  const int TY = xg.TY, H1 = xg.H1, H1p = xg.H1p, M = xg.M;
+  const int TY = xg.TY, H1p = xg.H1p, M = xg.M;
   const long long N3N2 = (long long)xg.N3 * xg.N2;
   const long long rowoff = (long long)l3 * xg.N2 + l2_0;
   const T* C = sizeof(T) == 8 ? reinterpret_cast<const T*>(d.C64) : reinterpret_cast<const T*>(d.C32);
   const uint16_t* ph = d.phase + ((long long)l3 * xg.N2 + l2_0) * xg.N1;
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);  // 6*TY lines of M (pitch H1p)
   cpx<T>* twl = buf + 6 * TY * H1p;
   for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  const int nload = 6 * TY * H1;
-  const int nlines = 6 * TY;
-  const int kh = M / 2 + 1;  // pair items per line
+  const int kh = M / 2 + 1;             // (k, M-k) pairs per line, k = 0..M/2
+  const int npair = 6 * kh * TY;
   const LdsAcc<T> lds{buf, H1p, 1};
-  constexpr int NPT = 8;  // loads in flight per thread per batch
+  const cpx<T>* src = reinterpret_cast<const cpx<T>*>(d.spec) + (long long)half * 6 * xg.S + rowoff;
+  cpx<T>* dst = reinterpret_cast<cpx<T>*>(d.spec) + (long long)half * 6 * xg.S + rowoff;
 
-  {
-    const cpx<T>* src = reinterpret_cast<const cpx<T>*>(d.spec) + (long long)half * 6 * xg.S;
+  // 1) load half-spectrum pairs X[k], X[M-k] of each row and apply the C2R split
+  //    Z[k] = X[k] + conj(X[M-k]) + i w^k (X[k] - conj(X[M-k])),  w = exp(2 pi i / N1)
+  constexpr int NPT = 4;
 #pragma unroll 1
-    for (int f0 = 0; f0 < nload; f0 += NPT * kThreads) {
-      T re[NPT], im[NPT];
+  for (int p0 = 0; p0 < npair; p0 += NPT * kThreads) {
+    cpx<T> xa[NPT], xb[NPT];
 #pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        const int f = min(f0 + (int)threadIdx.x + i * kThreads, nload - 1);
-        const int r = f % TY, k = (f / TY) % H1, c = f / (TY * H1);
-        const cpx<T> v = src[c * xg.S + k * N3N2 + rowoff + r];
-        re[i] = v.x;
-        im[i] = v.y;
-      }
+    for (int i = 0; i < NPT; ++i) {
+      const int p = min(p0 + (int)threadIdx.x + i * kThreads, npair - 1);
+      const int q = fdiv(p, xg.rTY), r = p - q * TY;
+      const int c = fdiv(q, xg.rKH), kk = q - c * kh;
+      const cpx<T>* s = src + c * xg.S + r;
+      xa[i] = s[kk * N3N2];
+      xb[i] = s[(M - kk) * N3N2];
+    }
 #pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        const int f = f0 + threadIdx.x + i * kThreads;
-        if (f < nload) {
-          const int r = f % TY, k = (f / TY) % H1, c = f / (TY * H1);
-          buf[(c * TY + r) * H1p + k] = cpx<T>{re[i], im[i]};
+    for (int i = 0; i < NPT; ++i) {
+      const int p = p0 + threadIdx.x + i * kThreads;
+      if (p < npair) {
+        const int q = fdiv(p, xg.rTY), r = p - q * TY;
+        const int c = fdiv(q, xg.rKH), kk = q - c * kh;
+        cpx<T>* Z = buf + (c * TY + r) * H1p;
+        const cpx<T> a = xa[i], b = xb[i];
+        if (kk == 0) {
+          Z[0] = (a + conjg(b)) + mul_i(a - conjg(b));
+        } else {
+          const int k2 = M - kk;
+          Z[kk] = (a + conjg(b)) + mul_i(conjg(twN1[kk]) * (a - conjg(b)));
+          if (k2 != kk) Z[k2] = (b + conjg(a)) + mul_i(conjg(twN1[k2]) * (b - conjg(a)));
         }
       }
     }
-    __syncthreads();
-    // C2R split: Z[k] = X[k] + conj(X[M-k]) + i w^k (X[k] - conj(X[M-k])), w = exp(2 pi i / N1)
-    for (int it = threadIdx.x; it < nlines * kh; it += kThreads) {
-      const int line = it / kh, kk = it - line * kh;
-      cpx<T>* X = buf + line * H1p;
-      if (kk == 0) {
-        const cpx<T> a = X[0], b = conjg(X[M]);
-        X[0] = (a + b) + mul_i(a - b);
-      } else {
-        const int k1 = kk, k2 = M - kk;
-        const cpx<T> a = X[k1], b = X[k2];
-        const cpx<T> w1 = conjg(twl[k1]);
-        const cpx<T> z1 = (a + conjg(b)) + mul_i(w1 * (a - conjg(b)));
-        if (k2 != k1) {
-          const cpx<T> w2 = conjg(twl[k2]);
-          X[k2] = (b + conjg(a)) + mul_i(w2 * (b - conjg(a)));
-        }
-        X[k1] = z1;
-      }
+  }
+  __syncthreads();
+  // 2) complex inverse transforms of length M: z[n] = x[2n] + i x[2n+1]
+  fft_lines<T, emax<T>(), true>(*planM, 6 * TY, 0.f, true, twl, 2, lds, lds, lds);
+  __syncthreads();
+  // 3) constitutive law on voxel pairs (2n, 2n+1): real / imaginary parts
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int it = threadIdx.x; it < TY * M; it += kThreads) {
+    const int r = fdiv(it, xg.rM), n = it - r * M;
+    T ea[6], eb[6], sa[6], sb[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const cpx<T> z = buf[(c * TY + r) * H1p + n];
+      ea[c] = z.x;
+      eb[c] = z.y;
     }
-    __syncthreads();
-    fft_lines<T, emax<T>(), true>(*planM, nlines, true, twl, 2, lds, lds, lds);
-    __syncthreads();
-    // constitutive law on voxel pairs (2n, 2n+1): real / imaginary parts
-    for (int it = threadIdx.x; it < TY * M; it += kThreads) {
-      const int r = it / M, n = it - r * M;
-      T ea[6], eb[6], sa[6], sb[6];
+    const int pa = ph[r * xg.N1 + 2 * n], pb = ph[r * xg.N1 + 2 * n + 1];
+    if (d.iso) {
+      const cpx<T> la = reinterpret_cast<const cpx<T>*>(C)[pa], lb = reinterpret_cast<const cpx<T>*>(C)[pb];
+      constitutive_iso<T>(la.x, la.y, d.Ebar, ea, sa);
+      constitutive_iso<T>(lb.x, lb.y, d.Ebar, eb, sb);
+    } else {
+      constitutive<T>(C + pa * 24, d.Ebar, ea, sa);
+      constitutive<T>(C + pb * 24, d.Ebar, eb, sb);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      acc[c] += 0.5 * ((double)sa[c] + (double)sb[c]);
+      buf[(c * TY + r) * H1p + n] = cpx<T>{sa[c], sb[c]};
+    }
+    if (xg.fields) {
+      const long long vox = ((long long)l3 * xg.N2 + l2_0 + r) * xg.N1 + 2 * n;
+      const long long Nn = (long long)xg.N1 * xg.N2 * xg.N3;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        const cpx<T> z = buf[(c * TY + r) * H1p + n];
-        ea[c] = z.x;
-        eb[c] = z.y;
-      }
-      const int pa = ph[r * xg.N1 + 2 * n], pb = ph[r * xg.N1 + 2 * n + 1];
-      constitutive<T>(C + pa * 36, d.Ebar, ea, sa);
-      constitutive<T>(C + pb * 36, d.Ebar, eb, sb);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        acc[c] += 0.5 * ((double)sa[c] + (double)sb[c]);
-        buf[(c * TY + r) * H1p + n] = cpx<T>{sa[c], sb[c]};
-      }
-      if (xg.fields) {
-        const long long vox = ((long long)l3 * xg.N2 + l2_0 + r) * xg.N1 + 2 * n;
-        const long long Nn = (long long)xg.N1 * xg.N2 * xg.N3;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          const double e0 = 0.5 * ((double)d.Ebar[c] + (double)ea[c]);
-          const double e1 = 0.5 * ((double)d.Ebar[c] + (double)eb[c]);
-          const double s0 = 0.5 * (double)sa[c], s1 = 0.5 * (double)sb[c];
-          if (half == 0) {
-            d.eps_out[c * Nn + vox] = e0; d.eps_out[c * Nn + vox + 1] = e1;
-            d.sig_out[c * Nn + vox] = s0; d.sig_out[c * Nn + vox + 1] = s1;
-          } else {
-            d.eps_out[c * Nn + vox] += e0; d.eps_out[c * Nn + vox + 1] += e1;
-            d.sig_out[c * Nn + vox] += s0; d.sig_out[c * Nn + vox + 1] += s1;
-          }
+        const double e0 = 0.5 * ((double)d.Ebar[c] + (double)ea[c]);
+        const double e1 = 0.5 * ((double)d.Ebar[c] + (double)eb[c]);
+        const double s0 = 0.5 * (double)sa[c], s1 = 0.5 * (double)sb[c];
+        if (half == 0) {
+          d.eps_out[c * Nn + vox] = e0; d.eps_out[c * Nn + vox + 1] = e1;
+          d.sig_out[c * Nn + vox] = s0; d.sig_out[c * Nn + vox + 1] = s1;
+        } else {
+          d.eps_out[c * Nn + vox] += e0; d.eps_out[c * Nn + vox + 1] += e1;
+          d.sig_out[c * Nn + vox] += s0; d.sig_out[c * Nn + vox + 1] += s1;
         }
       }
     }
-    __syncthreads();
-    fft_lines<T, emax<T>(), false>(*planM, nlines, true, twl, 2, lds, lds, lds);
-    __syncthreads();
-    // R2C merge: X[k] = (A - i w^-k B)/2 with A = Z[k] + conj(Z[M-k]), B = Z[k] - conj(Z[M-k])
-    const T hs = (T)(0.5 * xg.invN);
-    for (int it = threadIdx.x; it < nlines * kh; it += kThreads) {
-      const int line = it / kh, kk = it - line * kh;
-      cpx<T>* Z = buf + line * H1p;
-      if (kk == 0) {
-        const cpx<T> z = Z[0];
-        Z[0] = cpx<T>{(z.x + z.y) * (T)xg.invN, (T)0};
-        Z[M] = cpx<T>{(z.x - z.y) * (T)xg.invN, (T)0};
-      } else {
-        const int k1 = kk, k2 = M - kk;
-        const cpx<T> a = Z[k1], b = Z[k2];
-        const cpx<T> x1 = scale((a + conjg(b)) - mul_i(twl[k1] * (a - conjg(b))), hs);
-        if (k2 != k1) Z[k2] = scale((b + conjg(a)) - mul_i(twl[k2] * (b - conjg(a))), hs);
-        Z[k1] = x1;
-      }
+  }
+  __syncthreads();
+  // 4) forward transforms of length M
+  fft_lines<T, emax<T>(), false>(*planM, 6 * TY, 0.f, true, twl, 2, lds, lds, lds);
+  __syncthreads();
+  // 5) R2C merge straight to HBM (with the 1/N of eq. FT):
+  //    X[k] = (A - i w^-k B)/2, A = Z[k] + conj(Z[M-k]), B = Z[k] - conj(Z[M-k]);
+  //    X[0] = Re Z0 + Im Z0, X[M] = Re Z0 - Im Z0
+  const T hs = (T)(0.5 * xg.invN), sN = (T)xg.invN;
+  for (int p = threadIdx.x; p < npair; p += kThreads) {
+    const int q = fdiv(p, xg.rTY), r = p - q * TY;
+    const int c = fdiv(q, xg.rKH), kk = q - c * kh;
+    const cpx<T>* Z = buf + (c * TY + r) * H1p;
+    cpx<T>* o = dst + c * xg.S + r;
+    if (kk == 0) {
+      const cpx<T> z = Z[0];
+      o[0] = cpx<T>{(z.x + z.y) * sN, (T)0};
+      o[M * N3N2] = cpx<T>{(z.x - z.y) * sN, (T)0};
+    } else {
+      const int k2 = M - kk;
+      const cpx<T> a = Z[kk], b = Z[k2];
+      o[kk * N3N2] = scale((a + conjg(b)) - mul_i(twN1[kk] * (a - conjg(b))), hs);
+      if (k2 != kk) o[k2 * N3N2] = scale((b + conjg(a)) - mul_i(twN1[k2] * (b - conjg(a))), hs);
     }
-    __syncthreads();
-    cpx<T>* dst = reinterpret_cast<cpx<T>*>(d.spec) + (long long)half * 6 * xg.S;
-    for (int f = threadIdx.x; f < nload; f += kThreads) {
-      const int r = f % TY, k = (f / TY) % H1, c = f / (TY * H1);
-      dst[c * xg.S + k * N3N2 + rowoff + r] = buf[(c * TY + r) * H1p + k];
-    }
-    __syncthreads();
   }
   block_sum<6>(acc, red);
   if (threadIdx.x == 0) {
-    double* p = d.part_sig + (long long)(xg.half >= 0 ? 2 * tile + half : tile) * 6;
+    double* pp = d.part_sig + (long long)(xg.half >= 0 ? 2 * tile + half : tile) * 6;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) p[c] = acc[c];
+    for (int c = 0; c < 6; ++c) pp[c] = acc[c];
   }
 }
 
@@ -416,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
   const int m = (ne + kThreads - 1) / kThreads;  // run length
   const int nruns = (N3 + m - 1) / m;
   for (int wk = threadIdx.x; wk < TX * nruns; wk += kThreads) {
-    const int col = wk % TX, run = wk / TX;
+    const int run = fdiv(wk, zg.rTX), col = wk - run * TX;
     {
       cpx<double> a1[3], b1[3], a2[3], b2[3];
       affine_symbols(t1, tw2[h2_0 + col], a1, b1, a2, b2);
@@ -467,13 +488,13 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
     }
   }
   __syncthreads();
-  fft_lines<T, emax<T>(), false>(*plan3, lines, false, twl, 1, lds, lds, lds);
+  fft_lines<T, emax<T>(), false>(*plan3, lines, zg.rLines, false, twl, 1, lds, lds, lds);
   __syncthreads();
   // phase C: Green operator and update at q = (h1, h2, h3)
   double part[1] = {0.0};
   const double w = (h1 == 0 || 2 * h1 == zg.N1) ? 1.0 : 2.0;
   for (int e = threadIdx.x; e < ne; e += kThreads) {
-    const int col = e % TX, h3 = e / TX;
+    const int h3 = fdiv(e, zg.rTX), col = e - h3 * TX;
     const int h2 = h2_0 + col;
     const long long o = (long long)h3 * N2 + col;
     cpx<double> r[3];
@@ -499,17 +520,26 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
 #pragma unroll
       for (int k = 0; k < 3; ++k) Mjk[j][k] = 2.0 * (D1[j].x * D1[k].x + D1[j].y * D1[k].y);
     double K[3][3];
+    if (d.c0_iso) {
+      // isotropic lambda0: K = mu0 tr(M) I + (lam0 + mu0) M
+      const double tm = d.mu0 * (Mjk[0][0] + Mjk[1][1] + Mjk[2][2]), lm = d.lam0 + d.mu0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        double acc = 0.0;
+        for (int l = 0; l < 3; ++l) K[i][l] = lm * Mjk[i][l] + (i == l ? tm : 0.0);
+    } else {
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-          for (int k = 0; k < 3; ++k) acc += d.C0[((i * 3 + j) * 3 + k) * 3 + l] * Mjk[j][k];
-        K[i][l] = acc;
-      }
+        for (int l = 0; l < 3; ++l) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += d.C0[((i * 3 + j) * 3 + k) * 3 + l] * Mjk[j][k];
+          K[i][l] = acc;
+        }
+    }
     const bool sing = (h1 == 0 && h2 == 0 && h3 == 0) || (2 * h1 == zg.N1 && 2 * h2 == N2 && 2 * h3 == N3);
     // Omega = K^-1 by the adjugate (K symmetric)
     const double a00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];

@@ -103,6 +103,17 @@ def test_fp64_iterates_match_oracle(shape, n_phases, seed, kind, voids, K):
     check_pair(shape, g, r, ref, K)
 
 
+def test_fully_anisotropic_reference_medium():
+    """Generic (non-isotropic) reference medium: the Green operator path that contracts
+    the full lambda0 tensor (eq. Green_tensor) rather than the isotropic closed form."""
+    shape = (12, 10, 16)
+    ph, C, _, E = random_problem(shape, 3, 21, "aniso")
+    rng = np.random.default_rng(22)
+    C0 = syn.random_spd_voigt(rng, 6.0, 14.0)
+    g, r, ref = run_pair(shape, ph, C, C0, E, 4)
+    check_pair(shape, g, r, ref, 4)
+
+
 def test_sphere16_converged_ceff_matches_oracle_iterate_matched():
     """16^3 centred sphere, contrast 10: GPU C_eff at its stop iterate vs the oracle at
     the same iterate (<= 1e-10 relative), and the same stop iterate up to one step."""
