@@ -14,7 +14,7 @@ Prints ONE JSON line:
                  HIP-event duration, against 8 TB/s
   cpu_baseline   the CPU oracle timed on the host on a bounded sample
   time_to_1e-6   FP32+refinement vs plain FP64 device time to an FP64-verified
-                 residual of 1e-6 on the same workload
+                 residual of 1e-6 on the 256^3 Voronoi polycrystal (6 loads)
 """
 import argparse
 import hashlib
@@ -82,6 +82,40 @@ def cpu_baseline(problem, max_seconds=25.0):
                       f"{dt:.1f} s wall"}
 
 
+def time_to_tol(syn, hz, np, torch, n):
+    """Device time to an FP64-verified residual of 1e-6 on the periodic Voronoi
+    polycrystal (200 cubic grains C11=168, C12=121, C44=75, random orientations,
+    6 unit loads): plain FP64 iterations against FP32 iterations anchored by FP64
+    sweeps.  Each variant runs twice; the second run is reported."""
+    p = syn.polycrystal(shape=(n, n, n))
+    g = hz.Grid(*p.shape)
+    g.set_material(p.C, p.phase)
+    out = {"workload": f"voronoi{n}_200grains_cubic_6loads", "tol": 1e-6}
+    res = {}
+    for prec, name in ((hz.HZ_FP64, "fp64"), (hz.HZ_FP32_REFINE, "fp32_refine")):
+        g.bind(prec, 6)
+        for rep in range(2):
+            if rep == 1:
+                g.profile(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = g.solve(p.loads, C0=p.C0, tol=1e-6, precision=prec, check_every=4)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        g.profile(False)
+        prof = g.profile_read()
+        res[name] = r
+        out[name] = {"seconds_to_1e-6": round(float(np.max(r.seconds_to_1e6)), 4), "wall_s": round(wall, 4),
+                     "iters": int(np.max(r.iters)), "outer_rounds": int(np.max(r.outer_rounds)),
+                     "residual": float(np.max(r.residual)),
+                     "kernel_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in prof.items()}}
+    out["speedup"] = round(out["fp64"]["seconds_to_1e-6"] / out["fp32_refine"]["seconds_to_1e-6"], 3)
+    m64, m32 = res["fp64"].mean_sigma, res["fp32_refine"].mean_sigma
+    out["ceff_rel_diff_fp32r_vs_fp64"] = float(np.abs(m32 - m64).max() / np.abs(m64).max())
+    del g
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +124,7 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-6 comparison")
+    ap.add_argument("--ttt-n", type=int, default=256, help="grid size of the time-to-1e-6 polycrystal")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
     a = ap.parse_args()
@@ -168,17 +203,7 @@ def main():
 
     ttt = None
     if not a.no_ttt:
-        log("bench: time to 1e-6, FP64 vs FP32+refine")
-        r64 = g.solve(p.loads, C0=p.C0, tol=1e-6, check_every=4)
-        g.bind(hz.HZ_FP32_REFINE, 6)
-        r32 = g.solve(p.loads, C0=p.C0, tol=1e-6, precision=hz.HZ_FP32_REFINE, check_every=4)
-        dC = np.abs(r32.mean_sigma - r64.mean_sigma).max() / np.abs(r64.mean_sigma).max()
-        ttt = {"fp64_s": round(float(np.max(r64.seconds_to_1e6)), 4),
-               "fp32_refine_s": round(float(np.max(r32.seconds_to_1e6)), 4),
-               "speedup": round(float(np.max(r64.seconds_to_1e6) / np.max(r32.seconds_to_1e6)), 3),
-               "fp64_iters": int(np.max(r64.iters)), "fp32_inner_iters": int(np.max(r32.iters)),
-               "outer_rounds": int(np.max(r32.outer_rounds)),
-               "ceff_rel_diff_fp32r_vs_fp64": float(dC)}
+        ttt = time_to_tol(syn, hz, np, torch, a.ttt_n)
         log(f"bench: ttt {ttt}")
 
     cpu = None

@@ -201,7 +201,7 @@ def voronoi(shape, n_grains: int, seed: int):
     gz, gy, gx = np.meshgrid(np.arange(N3), np.arange(N2), np.arange(N1), indexing="ij")
     pts = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1).astype(np.float64)
     # points exactly on the upper box face are folded back by the periodic tree
-    _, idx = tree.query(pts, k=1)
+    _, idx = tree.query(pts, k=1, workers=-1)
     return idx.reshape(N3, N2, N1).astype(np.uint16), rng
 
 

@@ -343,6 +343,6 @@ __device__ __forceinline__ void fft_lines(const Plan& plan, int lines, float rli
 
 // elements per thread in one transform call (bounds register use)
 template <typename T>
-constexpr int emax() { return 16; }
+constexpr int emax() { return sizeof(T) == 8 ? 16 : 32; }
 
 }  // namespace hz

@@ -630,6 +630,23 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
   if (k == 0) s[ST_FIRST_ERR] = err;
   s[ST_K] = k + 1;
   if (fg.mode == 1) return;  // the host decides after a sweep
+  if (fg.mode == 3) {
+    // plain FP32 iterations of refinement round 0: stop at the target, at the FP32
+    // rounding floor (less than 3% gain over 32 iterations) or at the cap
+    const bool reached = err <= s[ST_REF];
+    const bool bad = !(err == err) || isinf(err) || (k > 0 && err > 1e3 * s[ST_FIRST_ERR]);
+    bool stalled = false;
+    if (k > 0 && (k % 32) == 0) {
+      if (err > 0.97 * s[ST_BEST]) stalled = true;
+      else s[ST_BEST] = err;
+    }
+    if (reached || bad || stalled || k + 1 >= fg.inner_max) {
+      s[ST_DONE] = bad ? 3.0 : 1.0;
+      s[ST_ITERS] = k + 1;
+      s[ST_PARITY] = 1 - fg.parity;
+    }
+    return;
+  }
   const bool stop = d.fixed_iters >= 0 ? (k >= d.fixed_iters) : (err < d.tol);
   const bool bad = !(err == err) || isinf(err) || (k > 0 && err > 1e3 * s[ST_FIRST_ERR]);
   if (stop || bad || k >= d.max_iters) {
