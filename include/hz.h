@@ -48,6 +48,7 @@ extern "C" {
 #define HZ_OK 0
 #define HZ_NOT_CONVERGED 1   /* max_iters reached; outputs written from the last iterate  */
 #define HZ_STAGNATED 2       /* refinement stopped gaining above tol (rounding floor)      */
+#define HZ_PENDING 3         /* hz_server_query: the request has not finished yet          */
 #define HZ_EINVAL (-1)       /* NULL pointer, size <= 0, unsupported size or option        */
 #define HZ_EODD (-2)         /* a grid dimension is odd (the scheme needs even N_i)        */
 #define HZ_ENOMATERIAL (-3)  /* hz_set_material not called                                */
@@ -88,6 +89,8 @@ typedef struct {
   double residual;          /* eps of the reported iterate, measured in FP64                    */
   double seconds;           /* device time from solve start to the reported iterate            */
   double seconds_to_1e6;    /* device time to the first FP64-verified eps < 1e-6, or -1         */
+  double wall_seconds;      /* host wall time: the hz_solve call, or a served request from
+                               submission to the step that saw it finish (queueing included)     */
 } hz_info;
 
 /* Fill *o with defaults: tol 1e-8, max_iters 2000, HZ_FP64, automatic reference,
@@ -149,6 +152,67 @@ int hz_profile_read(hz_grid g, int32_t max, const char** names, double* total_ms
 
 void hz_destroy_grid(hz_grid g);
 const char* hz_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Solve server: continuous batching of homogenization requests.
+ *
+ * A request is one grid's material (as set when it is submitted) with n_loads
+ * applied strains and its own options; requests on different grids, shapes,
+ * materials and precisions run together.  hz_server_step performs one tick:
+ * it admits queued requests in arrival order while their buffers fit the
+ * server's workspace and slots, runs check_every iterations of every active
+ * load (one launch per pass for all loads of one grid shape and kernel
+ * precision), reads the device stop flags once and retires the requests whose
+ * loads have all stopped, freeing their memory for the queue.  Each load keeps
+ * its own buffers, descriptor and device-side stop rule, so a request's
+ * results do not depend on what else is being served.
+ *
+ * Memory: one caller-owned device buffer; the first hz_server_bytes(max_problems)
+ * bytes hold the server tables, the rest is an arena for per-shape tables,
+ * per-material tables (shared by requests on the same material) and per-load
+ * buffers (hz_request_bytes).  The library allocates no device memory.
+ * A server is driven from one host thread; it owns its stream's ordering.
+ * After an HZ_EHIP error the server must be destroyed.
+ * ------------------------------------------------------------------------ */
+typedef struct hz_server_s* hz_server;
+
+/* Bytes of the fixed server tables for up to max_problems loads in flight. */
+int64_t hz_server_bytes(int32_t max_problems);
+
+/* Arena bytes one request needs: its per-load buffers plus the shape and
+ * material tables (the latter two are shared when already resident). */
+int64_t hz_request_bytes(hz_grid g, int32_t precision, int32_t n_loads);
+
+/* Create a server on a caller-owned device buffer (256-byte aligned) and HIP
+ * stream (may be NULL).  max_problems bounds the loads in flight (<= 4096);
+ * check_every is the number of iterations per tick. */
+int hz_server_create(void* dev_ptr, int64_t bytes, void* hip_stream, int32_t max_problems,
+                     int32_t check_every, hz_server* out);
+
+/* Queue a request: the material currently set on g (shared, copy-on-write: a
+ * later hz_set_material on g does not affect it), n_loads strains E[n_loads][6]
+ * and options o (tol, max_iters, precision, reference medium, inner_rho,
+ * inner_max; fixed_iters and traces are not served).  Writes the request id.
+ * HZ_EWORKSPACE if the request could never fit the workspace or slots. */
+int hz_server_submit(hz_server s, hz_grid g, int32_t n_loads, const double* E, const hz_opts* o,
+                     int64_t* id);
+
+/* One tick (admit, iterate, retire); *completed = requests finished in it. */
+int hz_server_step(hz_server s, int32_t* completed);
+
+/* HZ_PENDING while queued or running; once finished, fills sigma_mean[n_loads][6]
+ * and info[n_loads] (seconds counted from the tick the request started) and
+ * returns its worst per-load status as hz_solve does.  Either output may be NULL. */
+int hz_server_query(hz_server s, int64_t id, double* sigma_mean, hz_info* info);
+
+/* Forget a finished request, or withdraw a queued one (a running one: HZ_EINVAL). */
+int hz_server_release(hz_server s, int64_t id);
+
+/* Requests waiting for admission and requests running. */
+int hz_server_pending(hz_server s, int32_t* queued, int32_t* running);
+
+/* Wait for the stream and free the server's host state (the workspace stays the caller's). */
+void hz_server_destroy(hz_server s);
 
 #ifdef __cplusplus
 }

@@ -14,10 +14,10 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (HZ_EDIVERGED, HZ_FP32_REFINE, HZ_FP64, HZ_NOT_CONVERGED, HZ_OK, HZ_STAGNATED, HzError,
-                   check, hz_info, hz_opts)
+from ._abi import (HZ_EDIVERGED, HZ_FP32_REFINE, HZ_FP64, HZ_NOT_CONVERGED, HZ_OK, HZ_PENDING, HZ_STAGNATED,
+                   HzError, check, hz_info, hz_opts)
 
-__all__ = ["Grid", "SolveResult", "HZ_FP64", "HZ_FP32_REFINE", "HzError", "reference_medium", "lib"]
+__all__ = ["Grid", "Server", "SolveResult", "HZ_FP64", "HZ_FP32_REFINE", "HzError", "reference_medium", "lib"]
 
 
 def lib():
@@ -36,6 +36,35 @@ def reference_medium(C):
     return out.reshape(6, 6)
 
 
+def _opts(tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1, check_every=8, inner_rho=1e-3,
+          inner_max=400):
+    o = hz_opts()
+    lib().hz_default_opts(ctypes.byref(o))
+    o.tol = tol
+    o.max_iters = max_iters
+    o.precision = precision
+    o.fixed_iters = fixed_iters
+    o.check_every = check_every
+    o.inner_rho = inner_rho
+    o.inner_max = inner_max
+    if C0 is not None:
+        o.ref_mode = 1
+        o.ref_C[:] = np.asarray(C0, dtype=np.float64).reshape(36).tolist()
+    return o
+
+
+def _result(sm, infos, rc, **kw):
+    return SolveResult(
+        mean_sigma=sm,
+        status=np.array([i.status for i in infos]),
+        iters=np.array([i.iters for i in infos]),
+        outer_rounds=np.array([i.outer_rounds for i in infos]),
+        residual=np.array([i.residual for i in infos]),
+        seconds=np.array([i.seconds for i in infos]),
+        seconds_to_1e6=np.array([i.seconds_to_1e6 for i in infos]),
+        rc=rc, wall_seconds=np.array([i.wall_seconds for i in infos]), **kw)
+
+
 @dataclass
 class SolveResult:
     mean_sigma: np.ndarray          # [n_loads, 6] tensor comps
@@ -46,6 +75,7 @@ class SolveResult:
     seconds: np.ndarray
     seconds_to_1e6: np.ndarray
     rc: int
+    wall_seconds: np.ndarray | None = None
     trace_residual: np.ndarray | None = None   # [n_loads, T]
     trace_mean: np.ndarray | None = None       # [n_loads, T, 6]
     eps: np.ndarray | None = None              # [n_loads, 6, N3, N2, N1]
@@ -114,18 +144,7 @@ class Grid:
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
         nl = E.shape[0]
         self._ensure(precision, nl)
-        o = hz_opts()
-        lib().hz_default_opts(ctypes.byref(o))
-        o.tol = tol
-        o.max_iters = max_iters
-        o.precision = precision
-        o.fixed_iters = fixed_iters
-        o.check_every = check_every
-        o.inner_rho = inner_rho
-        o.inner_max = inner_max
-        if C0 is not None:
-            o.ref_mode = 1
-            o.ref_C[:] = np.asarray(C0, dtype=np.float64).reshape(36).tolist()
+        o = _opts(tol, max_iters, precision, C0, fixed_iters, check_every, inner_rho, inner_max)
         T = (fixed_iters if fixed_iters >= 0 else max_iters) + 1
         tr = tm = None
         if trace:
@@ -142,15 +161,7 @@ class Grid:
             sig = np.zeros((nl, 6, n3, n2, n1))
         rc = check(lib().hz_solve(self._h, nl, _dptr(E), ctypes.byref(o), _dptr(sm),
                                   _dptr(eps) if fields else None, _dptr(sig) if fields else None, infos))
-        return SolveResult(
-            mean_sigma=sm,
-            status=np.array([i.status for i in infos]),
-            iters=np.array([i.iters for i in infos]),
-            outer_rounds=np.array([i.outer_rounds for i in infos]),
-            residual=np.array([i.residual for i in infos]),
-            seconds=np.array([i.seconds for i in infos]),
-            seconds_to_1e6=np.array([i.seconds_to_1e6 for i in infos]),
-            rc=rc, trace_residual=tr, trace_mean=tm, eps=eps, sigma=sig)
+        return _result(sm, infos, rc, trace_residual=tr, trace_mean=tm, eps=eps, sigma=sig)
 
     def effective_stiffness(self, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, **kw):
         """C_eff (6x6 Voigt): column J = <sigma> of unit load gamma_J = 1, six loads in one batch."""
@@ -178,3 +189,78 @@ class Grid:
         cnt = (ctypes.c_int64 * n)()
         k = check(lib().hz_profile_read(self._h, n, names, ms, cnt))
         return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(k, n)) if cnt[i] > 0}
+
+
+def request_bytes(grid: "Grid", precision=HZ_FP64, n_loads=1) -> int:
+    """Arena bytes one served request on `grid` needs (buffers + shape and material tables)."""
+    return check(lib().hz_request_bytes(grid._h, precision, n_loads))
+
+
+class Server:
+    """Solve server (hz_server handle): continuous batching of requests on a
+    torch-owned workspace.  submit() queues a request, step() runs one tick
+    (admission, check_every iterations of every active load, retirement),
+    result() returns a finished request's SolveResult or None."""
+
+    def __init__(self, arena_bytes: int, max_problems=64, check_every=8, device="cuda", stream=None):
+        import torch
+
+        fixed = check(lib().hz_server_bytes(max_problems))
+        self._ws = torch.empty(fixed + int(arena_bytes), dtype=torch.uint8, device=device)
+        s = stream if stream is not None else torch.cuda.current_stream(self._ws.device)
+        self._stream = s
+        h = ctypes.c_void_p()
+        check(lib().hz_server_create(ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+                                     ctypes.c_void_p(s.cuda_stream), max_problems, check_every, ctypes.byref(h)))
+        self._h = h
+        self._nloads = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().hz_server_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def submit(self, grid: "Grid", E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, inner_rho=1e-3,
+               inner_max=400) -> int:
+        E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
+        o = _opts(tol, max_iters, precision, C0, -1, 8, inner_rho, inner_max)
+        rid = ctypes.c_int64()
+        check(lib().hz_server_submit(self._h, grid._h, E.shape[0], _dptr(E), ctypes.byref(o), ctypes.byref(rid)))
+        self._nloads[rid.value] = E.shape[0]
+        return rid.value
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        check(lib().hz_server_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def pending(self):
+        q = ctypes.c_int32()
+        r = ctypes.c_int32()
+        check(lib().hz_server_pending(self._h, ctypes.byref(q), ctypes.byref(r)))
+        return q.value, r.value
+
+    def result(self, rid: int, release=True):
+        nl = self._nloads[rid]
+        sm = np.zeros((nl, 6))
+        infos = (hz_info * nl)()
+        rc = check(lib().hz_server_query(self._h, rid, _dptr(sm), infos))
+        if rc == HZ_PENDING:
+            return None
+        if release:
+            check(lib().hz_server_release(self._h, rid))
+            del self._nloads[rid]
+        return _result(sm, infos, rc)
+
+    def drain(self, max_ticks=1 << 20):
+        """Step until nothing is queued or running."""
+        for _ in range(max_ticks):
+            q, r = self.pending()
+            if q == 0 and r == 0:
+                return
+            self.step()
+        raise RuntimeError("server did not drain")

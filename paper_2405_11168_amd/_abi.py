@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libhz.so")
 HZ_OK = 0
 HZ_NOT_CONVERGED = 1
 HZ_STAGNATED = 2
+HZ_PENDING = 3
 HZ_EINVAL = -1
 HZ_EODD = -2
 HZ_ENOMATERIAL = -3
@@ -46,6 +47,7 @@ class hz_info(ctypes.Structure):
         ("residual", c_double),
         ("seconds", c_double),
         ("seconds_to_1e6", c_double),
+        ("wall_seconds", c_double),
     ]
 
 
@@ -65,6 +67,16 @@ SIGNATURES = {
     "hz_profile_read": (c_int32, [c_void_p, c_int32, POINTER(c_char_p), POINTER(c_double), POINTER(c_int64)]),
     "hz_destroy_grid": (None, [c_void_p]),
     "hz_last_error": (c_char_p, []),
+    "hz_server_bytes": (c_int64, [c_int32]),
+    "hz_request_bytes": (c_int64, [c_void_p, c_int32, c_int32]),
+    "hz_server_create": (c_int32, [c_void_p, c_int64, c_void_p, c_int32, c_int32, POINTER(c_void_p)]),
+    "hz_server_submit": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(c_double), POINTER(hz_opts),
+                                   POINTER(c_int64)]),
+    "hz_server_step": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "hz_server_query": (c_int32, [c_void_p, c_int64, POINTER(c_double), POINTER(hz_info)]),
+    "hz_server_release": (c_int32, [c_void_p, c_int64]),
+    "hz_server_pending": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "hz_server_destroy": (None, [c_void_p]),
 }
 
 _lib = None

@@ -54,8 +54,15 @@ struct Desc {
   int max_iters;
   int fixed_iters;
   int trace_len;
+  int cmode;             // contraction: 0 update u, 1 FP64 sweep (store r), 2 update with r32 added
+  int fmode;             // stop rule: 0 plain, 1 sweep (measure only), 2 correction round, 3 FP32 round 0
+  int src;               // expansion source: 0 u[parity], 1 FP64 anchor u64
+  int inner_max;         // iteration cap of FP32 rounds
   int pad;
 };
+// The ping-pong slot of the current iterate is status[ST_K] & 1: every problem
+// counts its own measured iterates, so problems that started at different times
+// can share a launch.
 
 // Layout of Desc::status (doubles; integers stored exactly)
 enum St {
@@ -79,8 +86,6 @@ struct ZGeo {
   int N1, N2, N3, H1, TX, tiles;   // tiles = N2 / TX
   float rTX, rLines, rTiles;       // reciprocals of TX, 3 TX, tiles
   long long S;
-  int parity;
-  int src;                          // k_zexp: 0 = u[parity], 1 = FP64 anchor u64
 };
 
 // y pass geometry: contiguous rows of length N2, TX rows per tile
@@ -102,9 +107,6 @@ struct XGeo {
 struct FinGeo {
   int nbx, nbq;
   double invN;
-  int parity;
-  int mode;              // 0 plain iteration, 1 FP64 sweep, 2 inner refinement iteration
-  int inner_max;
 };
 
 }  // namespace hz

@@ -64,6 +64,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS, N
 }
 
 __device__ __forceinline__ bool problem_done(const Desc& d) { return d.status[ST_DONE] != 0.0; }
+// ping-pong slot holding the current iterate
+__device__ __forceinline__ int cur_slot(const Desc& d) { return ((int)d.status[ST_K]) & 1; }
 
 // D~ (tetrahedron T1) and D~2 (T2) at q from per-axis tables t_a = exp(-i q_a)
 __device__ __forceinline__ void symbols(cpx<double> t1, cpx<double> t2, cpx<double> t3,
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ desc
   for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
   const long long plane = (long long)h1 * N3 * N2 + h2_0;
   const LdsAcc<T> lds{buf, 1, lines};
-  const void* usrc = zg.src == 1 ? d.u64 : d.u[zg.parity];
+  const void* usrc = d.src == 1 ? d.u64 : d.u[cur_slot(d)];
   const GblAcc<T> src{reinterpret_cast<cpx<T>*>(const_cast<void*>(usrc)) + plane, (int)zg.S, TX, 1, N2};
   fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, src, lds);
   __syncthreads();
@@ -395,9 +397,9 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
 // formed before the forward z transform as R(l3) = A(l3) + B(l3 + 1) with
 // A = sigma.conj(alpha), B = sigma.conj(beta); then the transform of its 3 comps,
 // the Green operator in FP64 (eq. Green_tensor) and the update (eq. basic_scheme_dep_2).
-// MODE 0: u[1-parity] = u[parity] - Omega r
-// MODE 1: FP64 sweep of the anchor: store r in r32, no update
-// MODE 2: refinement inner step: r += r32, u[1-parity] = u[parity] - Omega r
+// d.cmode 0: u[1-p] = u[p] - Omega r      (p = current slot)
+// d.cmode 1: FP64 sweep of the anchor: store r in r32, no update
+// d.cmode 2: correction round: r += r32, u[1-p] = u[p] - Omega r
 // ----------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void sig_dot(const cpx<T> (&s)[6], const cpx<double>* c, cpx<double>* out) {
@@ -409,7 +411,7 @@ __device__ __forceinline__ void sig_dot(const cpx<T> (&s)[6], const cpx<double>*
   out[2] = s4 * c[0] + s3 * c[1] + s2 * c[2];
 }
 
-template <typename T, int MODE>
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ descs, const int* __restrict__ active,
                                                    ZGeo zg, const Plan* __restrict__ plan3, const cpx<T>* __restrict__ tw3T,
                                                    const cpx<double>* __restrict__ tw1,
@@ -500,6 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
     cpx<double> r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[c] = to64(lds.get(c * TX + col, h3));
+    const int MODE = d.cmode;
     if (MODE == 2) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) r[c] = r[c] + to64(reinterpret_cast<const cpx<float>*>(d.r32)[c * zg.S + plane + o]);
@@ -553,8 +556,9 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
     const double O[3][3] = {{a00 * inv, a01 * inv, a02 * inv},
                             {a01 * inv, a11 * inv, a12 * inv},
                             {a02 * inv, a12 * inv, a22 * inv}};
-    const cpx<T>* uin = reinterpret_cast<const cpx<T>*>(d.u[zg.parity]) + plane;
-    cpx<T>* uout = reinterpret_cast<cpx<T>*>(d.u[1 - zg.parity]) + plane;
+    const int p = cur_slot(d);
+    const cpx<T>* uin = reinterpret_cast<const cpx<T>*>(d.u[p]) + plane;
+    cpx<T>* uout = reinterpret_cast<cpx<T>*>(d.u[1 - p]) + plane;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const cpx<double> dw = {O[i][0] * r[0].x + O[i][1] * r[1].x + O[i][2] * r[2].x,
@@ -568,8 +572,8 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
 
 // ----------------------------------------------------------------------------
 // Fixed-order sums of the partials and the stop rule (eqs. L2-norm, tolerance).
-// MODE 0: plain iteration on u.  MODE 1: FP64 sweep (measure only).
-// MODE 2: inner refinement iteration (stop at ST_REF or on stagnation).
+// d.fmode 0: plain iteration on u.  1: FP64 sweep (measure only).
+// 2: correction round (stop at ST_REF or on stagnation).  3: FP32 round 0.
 // ----------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ descs,
@@ -578,7 +582,9 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
   const Desc& d = descs[active[blockIdx.x]];
   if (problem_done(d)) return;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
-  if (fg.mode != 2) {
+  const int fmode = d.fmode;
+  const int parity = cur_slot(d);
+  if (fmode != 2) {
     for (int b = threadIdx.x; b < fg.nbx; b += kThreads) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) v[c] += d.part_sig[(long long)b * 6 + c];
@@ -589,7 +595,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
   if (threadIdx.x != 0) return;
   double* s = d.status;
   const int k = (int)s[ST_K];
-  if (fg.mode == 2) {
+  if (fmode == 2) {
     // inner FP32 iteration: residual of U + delta relative to the sweep's ||<sigma>||
     const double err = sqrt(v[6]) / s[ST_NORM];
     s[ST_ERR] = err;
@@ -602,10 +608,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
       if (err > 0.97 * s[ST_BEST]) stalled = true;
       else s[ST_BEST] = err;
     }
-    if (reached || bad || stalled || k + 1 >= fg.inner_max) {
+    if (reached || bad || stalled || k + 1 >= d.inner_max) {
       s[ST_DONE] = bad ? 3.0 : 1.0;
       s[ST_ITERS] = k + 1;       // inner updates applied
-      s[ST_PARITY] = 1 - fg.parity;
+      s[ST_PARITY] = 1 - parity;
     }
     return;
   }
@@ -629,8 +635,13 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
   s[ST_NORM] = nrm;
   if (k == 0) s[ST_FIRST_ERR] = err;
   s[ST_K] = k + 1;
-  if (fg.mode == 1) return;  // the host decides after a sweep
-  if (fg.mode == 3) {
+  if (fmode == 1) {
+    // a sweep measures once; the host decides what follows
+    s[ST_DONE] = 1.0;
+    s[ST_ITERS] = k;
+    return;
+  }
+  if (fmode == 3) {
     // plain FP32 iterations of refinement round 0: stop at the target, at the FP32
     // rounding floor (less than 3% gain over 32 iterations) or at the cap
     const bool reached = err <= s[ST_REF];
@@ -640,10 +651,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
       if (err > 0.97 * s[ST_BEST]) stalled = true;
       else s[ST_BEST] = err;
     }
-    if (reached || bad || stalled || k + 1 >= fg.inner_max) {
+    if (reached || bad || stalled || k + 1 >= d.inner_max) {
       s[ST_DONE] = bad ? 3.0 : 1.0;
       s[ST_ITERS] = k + 1;
-      s[ST_PARITY] = 1 - fg.parity;
+      s[ST_PARITY] = 1 - parity;
     }
     return;
   }
@@ -652,7 +663,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
   if (stop || bad || k >= d.max_iters) {
     s[ST_DONE] = bad ? 3.0 : (stop ? 1.0 : 2.0);
     s[ST_ITERS] = k;
-    s[ST_PARITY] = fg.parity;
+    s[ST_PARITY] = parity;
   }
 }
 
@@ -718,20 +729,12 @@ hipError_t launch_xpass(const Desc* descs, const int* active, int nact, const XG
 }
 
 template <typename T>
-hipError_t launch_zcon(int mode, const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
+hipError_t launch_zcon(const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
                        const void* tw3T, const void* tw1, const void* tw2, const void* tw3, hipStream_t s) {
   const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
   dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
-  const cpx<T>* a = (const cpx<T>*)tw3T;
-  const cpx<double>* b = (const cpx<double>*)tw1;
-  const cpx<double>* c = (const cpx<double>*)tw2;
-  const cpx<double>* e = (const cpx<double>*)tw3;
-  if (mode == 0)
-    hipLaunchKernelGGL((k_zcon<T, 0>), grid, dim3(kThreads), shm, s, descs, active, zg, plan3, a, b, c, e);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_zcon<T, 1>), grid, dim3(kThreads), shm, s, descs, active, zg, plan3, a, b, c, e);
-  else
-    hipLaunchKernelGGL((k_zcon<T, 2>), grid, dim3(kThreads), shm, s, descs, active, zg, plan3, a, b, c, e);
+  hipLaunchKernelGGL(k_zcon<T>, grid, dim3(kThreads), shm, s, descs, active, zg, plan3, (const cpx<T>*)tw3T,
+                     (const cpx<double>*)tw1, (const cpx<double>*)tw2, (const cpx<double>*)tw3);
   return hipGetLastError();
 }
 
@@ -761,7 +764,7 @@ template hipError_t launch_yline<double>(const Desc*, const int*, int, const YGe
 template hipError_t launch_yline<float>(const Desc*, const int*, int, const YGeo&, const Plan*, const void*, bool, hipStream_t);
 template hipError_t launch_xpass<double>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
 template hipError_t launch_xpass<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
-template hipError_t launch_zcon<double>(int, const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
-template hipError_t launch_zcon<float>(int, const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
+template hipError_t launch_zcon<double>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
+template hipError_t launch_zcon<float>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
 
 }  // namespace hz

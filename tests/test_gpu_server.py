@@ -1,0 +1,140 @@
+"""Solve server (continuous batching): a request's results in a mix of
+requests on other grids, materials, shapes and precisions are bitwise those of
+the same request served alone, and of the same loads through hz_solve; every
+load keeps its own buffers, descriptor and device-side stop rule, so nothing
+it computes depends on its neighbours or on when it was admitted."""
+import numpy as np
+import pytest
+
+import hz_synth as syn
+import paper_2405_11168_amd as hz
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _grid(shape, seed, n_phases=2, aniso=False):
+    rng = np.random.default_rng(seed)
+    N1, N2, N3 = shape
+    ph = rng.integers(0, n_phases, (N3, N2, N1)).astype(np.uint16)
+    if aniso:
+        C = np.stack([syn.random_spd_voigt(rng, 0.5, 8.0) for _ in range(n_phases)])
+    else:
+        C = np.stack([syn.isotropic_voigt(float(E), 0.3) for E in 10.0 ** rng.uniform(0, 1.5, n_phases)])
+    g = hz.Grid(*shape)
+    g.set_material(C, ph)
+    return g
+
+
+def _loads(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(n, 6)) * 1e-3
+
+
+# (grid key, shape, seed, aniso, n_loads, precision, tol)
+CASES = [
+    ("a", (16, 16, 16), 1, False, 6, hz.HZ_FP64, 1e-8),
+    ("b", (12, 10, 8), 2, True, 2, hz.HZ_FP32_REFINE, 1e-8),
+    ("c", (16, 16, 16), 3, True, 3, hz.HZ_FP64, 1e-6),       # same shape as a, other material
+    ("d", (20, 12, 14), 4, False, 1, hz.HZ_FP32_REFINE, 1e-7),
+    ("a", (16, 16, 16), 1, False, 2, hz.HZ_FP32_REFINE, 1e-9),  # same material as the first
+]
+
+
+def _make():
+    grids = {}
+    for key, shape, seed, aniso, *_ in CASES:
+        if key not in grids:
+            grids[key] = _grid(shape, seed, aniso=aniso)
+    return grids
+
+
+def _arena(grids, factor=1.2):
+    total = 0
+    for i, (key, _s, _seed, _a, nl, prec, _t) in enumerate(CASES):
+        total += hz.request_bytes(grids[key], prec, nl)
+    return int(total * factor)
+
+
+def _alone(grids):
+    out = []
+    for i, (key, _s, _seed, _a, nl, prec, tol) in enumerate(CASES):
+        g = grids[key]
+        srv = hz.Server(hz.request_bytes(g, prec, nl), max_problems=8)
+        rid = srv.submit(g, _loads(nl, 100 + i), tol=tol, precision=prec)
+        srv.drain()
+        r = srv.result(rid)
+        assert r is not None and r.rc >= 0, r
+        out.append(r)
+    return out
+
+
+def _same(a, b):
+    return np.array_equal(a.mean_sigma, b.mean_sigma) and np.array_equal(a.iters, b.iters) and \
+        np.array_equal(a.status, b.status) and np.array_equal(a.residual, b.residual)
+
+
+def test_mix_equals_alone_bitwise():
+    grids = _make()
+    alone = _alone(grids)
+    srv = hz.Server(_arena(grids), max_problems=32, check_every=4)
+    ids = [srv.submit(grids[key], _loads(nl, 100 + i), tol=tol, precision=prec)
+           for i, (key, _s, _seed, _a, nl, prec, tol) in enumerate(CASES)]
+    srv.drain()
+    for i, rid in enumerate(ids):
+        r = srv.result(rid)
+        _say(f"  case {i}: iters {r.iters} rounds {r.outer_rounds} res {r.residual}")
+        assert _same(r, alone[i]), i
+    # the same loads through hz_solve (same executor, one group) agree bitwise too
+    for i, (key, _s, _seed, _a, nl, prec, tol) in enumerate(CASES):
+        rs = grids[key].solve(_loads(nl, 100 + i), tol=tol, precision=prec)
+        assert _same(rs, alone[i]), i
+
+
+def test_continuous_arrivals_and_admission_under_memory_pressure():
+    """Requests arrive while others run; the arena holds only about two requests,
+    so later ones wait in the queue and are admitted as memory frees up."""
+    grids = _make()
+    alone = _alone(grids)
+    biggest = max(hz.request_bytes(grids[k], p, n) for k, _s, _sd, _a, n, p, _t in CASES)
+    srv = hz.Server(int(2.05 * biggest), max_problems=16, check_every=2)
+    ids = {}
+    saw_queue = False
+    pending = list(range(len(CASES)))
+    tick = 0
+    while pending or any(srv.pending()):
+        if pending and tick % 3 == 0:  # one arrival every third tick
+            i = pending.pop(0)
+            key, _s, _sd, _a, nl, prec, tol = CASES[i]
+            ids[i] = srv.submit(grids[key], _loads(nl, 100 + i), tol=tol, precision=prec)
+        q, _r = srv.pending()
+        saw_queue |= q > 0
+        srv.step()
+        tick += 1
+        assert tick < 100000
+    assert saw_queue
+    for i, rid in ids.items():
+        r = srv.result(rid)
+        assert r is not None and _same(r, alone[i]), i
+        assert np.all(r.wall_seconds > 0)
+
+
+def test_release_of_queued_request_and_errors():
+    g = _grid((8, 8, 8), 9)
+    need = hz.request_bytes(g, hz.HZ_FP64, 1)
+    srv = hz.Server(need, max_problems=4, check_every=1)
+    a = srv.submit(g, _loads(1, 1), tol=1e-6)
+    b = srv.submit(g, _loads(1, 2), tol=1e-6)  # waits: the arena fits one request
+    srv.step()
+    q, r = srv.pending()
+    assert q == 1 and r == 1
+    assert hz.lib().hz_server_release(srv._h, b) == 0  # withdraw the queued one
+    assert hz.lib().hz_server_release(srv._h, a) == hz._abi.HZ_EINVAL  # running
+    srv.drain()
+    assert srv.result(a).rc >= 0
+    with pytest.raises(hz.HzError) as e:
+        srv.submit(g, _loads(2, 3), tol=1e-6)  # two loads never fit
+    assert e.value.code == hz._abi.HZ_EWORKSPACE
