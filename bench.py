@@ -15,6 +15,11 @@ Prints ONE JSON line:
   cpu_baseline   the CPU oracle timed on the host on a bounded sample
   time_to_1e-6   FP32+refinement vs plain FP64 device time to an FP64-verified
                  residual of 1e-6 on the 256^3 Voronoi polycrystal (6 loads)
+  serving        a seeded stream of solve requests (grid sizes 32..192^3, Boolean
+                 spheres or cubic polycrystals, contrast log-uniform 1e1..1e6, one
+                 load each, FP32+refine to 1e-6) through the solve server: closed-loop
+                 saturation throughput, then Poisson arrivals at 0.7x that rate with
+                 p50/p99 latency from arrival to result
 """
 import argparse
 import hashlib
@@ -116,6 +121,95 @@ def time_to_tol(syn, hz, np, torch, n):
     return out
 
 
+def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5):
+    """Closed loop (all requests at t=0) for the saturation rate, then an open
+    loop with Poisson arrivals at load_factor x that rate.  Latency = result
+    ready (the server step that retired the request) - arrival time."""
+    t0 = time.perf_counter()
+    reqs = [syn.serving_request(i) for i in range(n_req)]
+    grids = []
+    for p in reqs:
+        g = hz.Grid(*p.shape)
+        g.set_material(p.C, p.phase)
+        grids.append(g)
+    gen_s = time.perf_counter() - t0
+    need = [hz.request_bytes(g, hz.HZ_FP32_REFINE, 1) for g in grids]
+    arena = min(int(1.05 * sum(need)), 160 << 30)
+    srv = hz.Server(arena, max_problems=n_req + 8, check_every=8)
+
+    def submit(i):
+        p = reqs[i]
+        return srv.submit(grids[i], p.loads, tol=1e-6, precision=hz.HZ_FP32_REFINE, C0=p.C0, max_iters=max_iters)
+
+    # warm the kernels of every shape once (untimed)
+    seen = {}
+    for i, p in enumerate(reqs):
+        seen.setdefault(p.shape, i)
+    for i in seen.values():
+        submit(i)
+    srv.drain()
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        """arrivals[i] = seconds after start; returns per-request (latency, result)."""
+        order = np.argsort(arrivals, kind="stable")
+        ids, lat, res = {}, np.zeros(n_req), [None] * n_req
+        k = 0
+        start = time.perf_counter()
+        while k < n_req or ids:
+            now = time.perf_counter() - start
+            while k < n_req and arrivals[order[k]] <= now:
+                i = int(order[k])
+                ids[i] = submit(i)
+                k += 1
+            q, r = srv.pending()
+            if q == 0 and r == 0:
+                if k < n_req:
+                    time.sleep(max(0.0, arrivals[order[k]] - (time.perf_counter() - start)))
+                continue
+            if srv.step():
+                t = time.perf_counter() - start
+                for i in list(ids):
+                    out = srv.result(ids[i])
+                    if out is not None:
+                        lat[i] = t - arrivals[i]
+                        res[i] = out
+                        del ids[i]
+        return lat, res, time.perf_counter() - start
+
+    closed_lat, closed_res, makespan = run(np.zeros(n_req))
+    sat = n_req / makespan
+    rng = np.random.default_rng(seed)
+    rate = load_factor * sat
+    arr = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    arr -= arr[0]
+    lat, res, span = run(arr)
+    status = np.array([r.status[0] for r in res])
+    iters = np.array([r.iters[0] for r in res])
+    vox = np.array([np.prod(p.shape) for p in reqs], dtype=np.float64)
+    ok = status == hz.HZ_OK
+    names = {hz.HZ_OK: "ok", hz.HZ_NOT_CONVERGED: "not_converged", hz.HZ_STAGNATED: "stagnated",
+             hz._abi.HZ_EDIVERGED: "diverged"}
+    return {
+        "workload": f"{n_req} requests: n in {{32,48,64,96,128,160,192}}^3, Boolean spheres (R=n/16, vf 0.3) or "
+                    f"200-grain cubic polycrystal (Zener ratio = contrast), contrast log-uniform 1e1..1e6, one unit "
+                    f"load each, FP32+refine to 1e-6, max_iters {max_iters}",
+        "closed_loop": {"makespan_s": round(makespan, 3), "solves_per_s": round(sat, 3),
+                        "p50_s": round(float(np.percentile(closed_lat, 50)), 4),
+                        "p99_s": round(float(np.percentile(closed_lat, 99)), 4)},
+        "open_loop": {"arrival_rate_per_s": round(rate, 3), "load_factor": load_factor, "span_s": round(span, 3),
+                      "solves_per_s": round(n_req / span, 3),
+                      "p50_s": round(float(np.percentile(lat, 50)), 4),
+                      "p99_s": round(float(np.percentile(lat, 99)), 4),
+                      "p50_converged_s": round(float(np.percentile(lat[ok], 50)), 4) if ok.any() else None,
+                      "p99_converged_s": round(float(np.percentile(lat[ok], 99)), 4) if ok.any() else None},
+        "status_counts": {names.get(int(c), str(int(c))): int((status == c).sum()) for c in np.unique(status)},
+        "mean_fp32_iters": round(float(iters.mean()), 1),
+        "voxel_iters_per_s_closed_loop": float((vox * iters).sum() / makespan),
+        "arena_gib": round(arena / 2 ** 30, 2), "generation_s": round(gen_s, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +219,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-6 comparison")
     ap.add_argument("--ttt-n", type=int, default=256, help="grid size of the time-to-1e-6 polycrystal")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-n", type=int, default=64, help="requests in the serving stream")
+    ap.add_argument("--serve-max-iters", type=int, default=1000, help="iteration budget per served request")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
     a = ap.parse_args()
@@ -206,6 +303,12 @@ def main():
         ttt = time_to_tol(syn, hz, np, torch, a.ttt_n)
         log(f"bench: ttt {ttt}")
 
+    serving = None
+    if not a.no_serve:
+        log(f"bench: serving leg ({a.serve_n} requests)")
+        serving = serving_leg(syn, hz, np, torch, a.serve_n, a.serve_max_iters)
+        log(f"bench: serving {serving}")
+
     cpu = None
     if not a.no_cpu:
         log("bench: CPU oracle baseline (bounded sample)")
@@ -221,7 +324,7 @@ def main():
                    "precision": "fp64", "vf": round(p.info["vf"], 4), "n_spheres": p.info["n_spheres"],
                    "parallelism": "single GPU"},
         "roofline": roof, "iteration_roofline_frac_105unit_model": round(iter_frac, 4),
-        "per_kernel": per_kernel, "cpu_baseline": cpu, "time_to_1e-6": ttt, "serving": None,
+        "per_kernel": per_kernel, "cpu_baseline": cpu, "time_to_1e-6": ttt, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -47,7 +47,8 @@ extern "C" {
 
 #define HZ_OK 0
 #define HZ_NOT_CONVERGED 1   /* max_iters reached; outputs written from the last iterate  */
-#define HZ_STAGNATED 2       /* refinement stopped gaining above tol (rounding floor)      */
+#define HZ_STAGNATED 2       /* refinement: 3 FP64 sweeps in a row gained < 10% (a rounding
+                                floor above tol); U of the last sweep is reported         */
 #define HZ_PENDING 3         /* hz_server_query: the request has not finished yet          */
 #define HZ_EINVAL (-1)       /* NULL pointer, size <= 0, unsupported size or option        */
 #define HZ_EODD (-2)         /* a grid dimension is odd (the scheme needs even N_i)        */
