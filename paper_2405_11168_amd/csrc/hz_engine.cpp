@@ -22,6 +22,11 @@
 
 #include "hz_host.h"
 
+// rows per x-pass block at most (a compile-time tuning default)
+#ifndef HZ_TYX_CAP
+#define HZ_TYX_CAP 16
+#endif
+
 namespace hz {
 
 const char* const kKindNames[K_COUNT] = {"zexpand", "yinv", "xpass", "yfwd", "zcontract", "finalize", "accumulate",
@@ -106,7 +111,7 @@ void Shape::init(int n1, int n2, int n3) {
     TXy[d] = ty;
     // x kernel: 6 comps x TY rows x (N1/2+1) in LDS (+ N1 twiddles), TY | N2
     const int hp = (G.N1 / 2) | 1;  // lines hold M = N1/2 values; odd pitch spreads rows over banks
-    int tyx = std::min(16, G.N2);
+    int tyx = std::min(HZ_TYX_CAP, G.N2);
     while (tyx > 1 && ((6 * tyx * hp + G.N1) * csz > kLdsBytes || 6 * tyx * (G.N1 / 2) > tile || G.N2 % tyx)) --tyx;
     if ((6 * tyx * hp + G.N1) * csz > kLdsBytes || 6 * tyx * (G.N1 / 2) > tile) fail(HZ_EINVAL, "N1 too large");
     TYx[d] = tyx;
