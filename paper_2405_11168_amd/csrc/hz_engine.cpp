@@ -81,6 +81,55 @@ Plan make_plan(int L) {
   return p;
 }
 
+Plan plan_of(const std::vector<int>& v, int L) {
+  Plan p{};
+  p.L = L;
+  p.np = (int)v.size();
+  int ns = 1;
+  for (int s = 0; s < p.np; ++s) {
+    p.radix[s] = v[s];
+    p.rLR[s] = recip(L / v[s]);
+    p.rNs[s] = recip(ns);
+    ns *= v[s];
+  }
+  return p;
+}
+
+// Factorisation of M = N1/2 for the fused x pass: first radix in {16, 8, 4, 2}
+// (the load/split and merge/store stages), last radix in {5, 4, 3, 2} (the pass
+// the constitutive law sits between: 6 components of it stay in registers), at
+// least two passes and at most kThreads butterflies per line in the last one.
+// Returns false where the unfused pass is used.
+bool make_xplans(int M, Plan& inv, Plan& fwd) {
+  const Plan p = make_plan(M);
+  std::vector<int> v(p.radix, p.radix + p.np);
+  auto pow2 = [](int r) { return r == 16 || r == 8 || r == 4 || r == 2; };
+  if (v.empty()) return false;  // M = 1
+  if (v.back() == 7) {
+    // move a factor 2 from the first radix to the end
+    if (!pow2(v[0])) return false;
+    if (v[0] == 2) v.erase(v.begin());
+    else v[0] /= 2;
+    v.push_back(2);
+  }
+  if (v.back() == 16) {
+    v.back() = 4;
+    v.push_back(4);
+  } else if (v.back() == 8) {
+    v.back() = 2;
+    v.push_back(4);
+  } else if (v.size() == 1 && v[0] == 4) {
+    v = {2, 2};
+  }
+  const int last = v.back();
+  if (v.size() < 2 || !pow2(v[0]) || !(last == 5 || last == 4 || last == 3 || last == 2) || M / last > kThreads)
+    return false;
+  inv = plan_of(v, M);
+  std::reverse(v.begin(), v.end());
+  fwd = plan_of(v, M);
+  return true;
+}
+
 }  // namespace
 
 void Shape::init(int n1, int n2, int n3) {
@@ -95,6 +144,9 @@ void Shape::init(int n1, int n2, int n3) {
   plans[1] = make_plan(G.N2);
   plans[2] = make_plan(G.N3);
   plans[3] = make_plan(G.N1 / 2);
+  xfused = make_xplans(G.N1 / 2, plans[4], plans[5]);
+  // spectra are addressed with 32-bit offsets inside one load's 12 fields
+  if (12 * G.S >= (1LL << 31)) fail(HZ_EINVAL, "grid too large");
   for (int d = 0; d < 2; ++d) {
     const int csz = d ? 16 : 8;
     const int tile = (d ? 16 : 32) * kThreads;  // elements per transform call
@@ -111,9 +163,12 @@ void Shape::init(int n1, int n2, int n3) {
     TXy[d] = ty;
     // x kernel: 6 comps x TY rows x (N1/2+1) in LDS (+ N1 twiddles), TY | N2
     const int hp = (G.N1 / 2) | 1;  // lines hold M = N1/2 values; odd pitch spreads rows over banks
+    // (the whole-block transforms of the unfused pass, used for output fields, and the
+    // middle passes of the fused one hold at most `tile` elements)
+    auto x_fits = [&](int t) { return (6 * t * hp + G.N1) * csz <= kLdsBytes && 6 * t * (G.N1 / 2) <= tile; };
     int tyx = std::min(HZ_TYX_CAP, G.N2);
-    while (tyx > 1 && ((6 * tyx * hp + G.N1) * csz > kLdsBytes || 6 * tyx * (G.N1 / 2) > tile || G.N2 % tyx)) --tyx;
-    if ((6 * tyx * hp + G.N1) * csz > kLdsBytes || 6 * tyx * (G.N1 / 2) > tile) fail(HZ_EINVAL, "N1 too large");
+    while (tyx > 1 && (!x_fits(tyx) || G.N2 % tyx)) --tyx;
+    if (!x_fits(tyx)) fail(HZ_EINVAL, "N1 too large");
     TYx[d] = tyx;
     H1p[d] = hp;
     nbx[d] = 2 * G.N3 * (G.N2 / tyx);
@@ -128,7 +183,7 @@ size_t shape_table_bytes(const Shape& s) {
   const int Ns[3] = {s.geo.N1, s.geo.N2, s.geo.N3};
   size_t b = 0;
   for (int a = 0; a < 3; ++a) b += align_up((size_t)Ns[a] * 16) + align_up((size_t)Ns[a] * 8);
-  return b + align_up(4 * sizeof(Plan));
+  return b + align_up(sizeof(s.plans));
 }
 
 ShapeTables upload_shape_tables(const Shape& s, char* dev, hipStream_t st) {
@@ -447,18 +502,32 @@ void pass_front(Engine& e, const Shape& sh, const ShapeTables& tb, const int* ac
   L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], true, e.stream), "y inverse");
 }
 
-// P3: fused x pass; with fields, T1 writes and T2 then adds its half of the averages
+// P3: x pass; with fields, T1 writes and T2 then adds its half of the averages.  The
+// active list holds the n_iso problems with all-isotropic materials first.
 template <typename T>
-void pass_x(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int fields) {
+void pass_x(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso, int fields) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
   for (int h = fields ? 0 : -1; h < (fields ? 2 : 0); ++h) {
     const int M = G.N1 / 2;
-    const XGeo xg{G.N1, G.N2, G.N3, G.H1, sh.H1p[d], sh.TYx[d], M, recip(sh.TYx[d]), recip(M / 2 + 1), recip(M),
-                  G.S, 1.0 / (double)G.N, fields, h};
+    XGeo xg{G.N1, G.N2, G.N3, G.H1, sh.H1p[d], sh.TYx[d], M, recip(sh.TYx[d]), recip(M / 2 + 1), recip(M),
+            G.S, 1.0 / (double)G.N, fields, h, 1.0f, 1.0f};
     Launch L(e, K_XPASS, d);
-    L.done(launch_xpass<T>(e.d_desc, act, n, xg, tb.plans + 3, tw[0], e.stream), "x pass");
+    if (sh.xfused && !fields) {
+      const Plan& pi = sh.plans[4];
+      xg.rNI = recip(M / pi.radix[0] / 2 + 1);
+      xg.rLRm = recip(M / pi.radix[pi.np - 1]);
+      if (n_iso > 0)
+        L.done(launch_xfused<T>(e.d_desc, act, n_iso, true, xg, tb.plans + 4, tb.plans + 5, tw[0], e.stream),
+               "x pass");
+      if (n > n_iso)
+        L.done(launch_xfused<T>(e.d_desc, act + n_iso, n - n_iso, false, xg, tb.plans + 4, tb.plans + 5, tw[0],
+                                e.stream),
+               "x pass");
+    } else {
+      L.done(launch_xpass<T>(e.d_desc, act, n, xg, tb.plans + 3, tw[0], e.stream), "x pass");
+    }
   }
 }
 
@@ -485,9 +554,9 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
 }
 
 template <typename T>
-void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n) {
+void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso) {
   pass_front<T>(e, sh, tb, act, n);
-  pass_x<T>(e, sh, tb, act, n, 0);
+  pass_x<T>(e, sh, tb, act, n, n_iso, 0);
   pass_back<T>(e, sh, tb, act, n);
 }
 
@@ -617,7 +686,7 @@ std::vector<Prob*> Engine::tick() {
     int cat;  // 0 accumulate, 1 zero u0 FP64, 2 zero u0 FP32, 3 zero U, 4 iterate FP64, 5 iterate FP32
     const Prob* proto;
     std::vector<Prob*> ps;
-    int off = 0, K = 0, ev0 = 0;
+    int off = 0, K = 0, ev0 = 0, n_iso = 0;
   };
   std::vector<Seg> segs;
   auto put = [&](int cat, Prob* p) {
@@ -646,6 +715,13 @@ std::vector<Prob*> Engine::tick() {
     put(kernel_fp64(p->st) ? 4 : 5, p);
   }
   std::stable_sort(segs.begin(), segs.end(), [](const Seg& a, const Seg& b) { return a.cat < b.cat; });
+  // iterate groups list problems with all-isotropic materials first (the x pass has a
+  // kernel for each kind)
+  for (auto& s : segs)
+    if (s.cat >= 4) {
+      std::stable_partition(s.ps.begin(), s.ps.end(), [](const Prob* p) { return p->base.iso != 0; });
+      s.n_iso = (int)std::count_if(s.ps.begin(), s.ps.end(), [](const Prob* p) { return p->base.iso != 0; });
+    }
   int cur = 0;
   for (auto& s : segs) {
     s.off = cur;
@@ -692,8 +768,8 @@ std::vector<Prob*> Engine::tick() {
     const int* act = d_active + s.off;
     const int n = (int)s.ps.size();
     for (int i = 0; i < s.K; ++i) {
-      if (s.cat == 4) iteration<double>(*this, *s.proto->shape, s.proto->tab, act, n);
-      else iteration<float>(*this, *s.proto->shape, s.proto->tab, act, n);
+      if (s.cat == 4) iteration<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
+      else iteration<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
       hip_check(hipEventRecord(event(nev++), stream), "hipEventRecord");
     }
   }
@@ -849,7 +925,7 @@ void output_fields(Engine& e, Prob& p, double* eps_dev, double* sig_dev) {
             "status H2D");
   hip_check(hipMemcpyAsync(e.d_active, e.h_active, 4, hipMemcpyHostToDevice, e.stream), "active H2D");
   pass_front<double>(e, *p.shape, p.tab, e.d_active, 1);
-  pass_x<double>(e, *p.shape, p.tab, e.d_active, 1, 1);
+  pass_x<double>(e, *p.shape, p.tab, e.d_active, 1, p.base.iso ? 1 : 0, 1);
   hip_check(hipStreamSynchronize(e.stream), "sync");
   if (e.prof->on) e.prof->drain();
 }

@@ -15,6 +15,32 @@ struct alignas(2 * sizeof(T)) cpx {
   T x, y;
 };
 
+// Global-memory pointers.  Buffer pointers read from a descriptor are generic to
+// the compiler, which then emits flat memory instructions (they count against the
+// LDS wait counter too and need 64-bit address arithmetic per lane); casting them
+// to the global address space gives global loads/stores with scalar bases.
+#define HZ_GLB __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ HZ_GLB T* glb(T* p) { return (HZ_GLB T*)p; }
+template <typename T>
+__device__ __forceinline__ const HZ_GLB T* glb(const T* p) { return (const HZ_GLB T*)p; }
+// complex element load/store through a global pointer (one 8- or 16-byte access)
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Vec2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <typename T>
+__device__ __forceinline__ cpx<T> gld(const HZ_GLB cpx<T>* p) {
+  const typename Vec2<T>::type v = *reinterpret_cast<const HZ_GLB typename Vec2<T>::type*>(p);
+  return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void gst(HZ_GLB cpx<T>* p, cpx<T> a) {
+  typename Vec2<T>::type v;
+  v.x = a.x;
+  v.y = a.y;
+  *reinterpret_cast<HZ_GLB typename Vec2<T>::type*>(p) = v;
+}
+
 template <typename T>
 __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
@@ -192,14 +218,14 @@ struct LdsAcc {
 template <typename T>
 struct GblAcc {
   static constexpr bool kLds = false;
-  cpx<T>* p;
+  HZ_GLB cpx<T>* p;
   int B, G, sl, sj;
   __device__ __forceinline__ int at(int t, int j) const {
     const int q = t / G;
     return q * B + (t - q * G) * sl + j * sj;
   }
-  __device__ __forceinline__ cpx<T> get(int t, int j) const { return p[at(t, j)]; }
-  __device__ __forceinline__ void put(int t, int j, cpx<T> v) const { p[at(t, j)] = v; }
+  __device__ __forceinline__ cpx<T> get(int t, int j) const { return gld(p + at(t, j)); }
+  __device__ __forceinline__ void put(int t, int j, cpx<T> v) const { gst(p + at(t, j), v); }
 };
 
 // floor(a / d) for 0 <= a < 2^19 given r = (1 + 2^-20)/d rounded up (see Plan)

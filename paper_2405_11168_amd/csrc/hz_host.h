@@ -22,6 +22,9 @@ hipError_t launch_yline(const Desc*, const int*, int, const YGeo&, const Plan*, 
 template <typename T>
 hipError_t launch_xpass(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
 template <typename T>
+hipError_t launch_xfused(const Desc*, const int*, int, bool, const XGeo&, const Plan*, const Plan*, const void*,
+                         hipStream_t);
+template <typename T>
 hipError_t launch_zcon(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*,
                        const void*, hipStream_t);
 hipError_t launch_finalize(const Desc*, const int*, int, const FinGeo&, hipStream_t);
@@ -46,7 +49,8 @@ bool factor_ok(int n);
 // ---- grid shape: transform plans and tile sizes of every pass, both precisions
 struct Shape {
   Geo geo{};
-  Plan plans[4]{};  // N1, N2, N3, N1/2
+  Plan plans[6]{};  // N1, N2, N3, N1/2, fused x pass: inverse and forward factorisations of N1/2
+  bool xfused = false;  // the x pass runs in its fused form (needs >= 2 radix passes of N1/2)
   int TXz[2]{}, TXy[2]{}, TYx[2]{}, H1p[2]{};  // [0] FP32 kernels, [1] FP64 kernels
   int nbx[2]{}, nbq[2]{};                      // partial-sum blocks of the x and z passes
   void init(int n1, int n2, int n3);            // throws HzError for unsupported sizes

@@ -102,6 +102,7 @@ struct XGeo {
   double invN;
   int fields;            // write real-space eps/sigma (T1/T2 averages)
   int half;              // -1: both tetrahedra (two blocks per row tile); 0/1: only T1/T2
+  float rNI, rLRm;       // fused form: reciprocals of (M/r0)/2 + 1 and of M/r_last
 };
 
 struct FinGeo {

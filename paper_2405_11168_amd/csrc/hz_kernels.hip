@@ -141,10 +141,10 @@ __global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ desc
   const long long plane = (long long)h1 * N3 * N2 + h2_0;
   const LdsAcc<T> lds{buf, 1, lines};
   const void* usrc = d.src == 1 ? d.u64 : d.u[cur_slot(d)];
-  const GblAcc<T> src{reinterpret_cast<cpx<T>*>(const_cast<void*>(usrc)) + plane, (int)zg.S, TX, 1, N2};
+  const GblAcc<T> src{glb(reinterpret_cast<cpx<T>*>(const_cast<void*>(usrc))) + plane, (int)zg.S, TX, 1, N2};
   fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, src, lds);
   __syncthreads();
-  cpx<T>* out = reinterpret_cast<cpx<T>*>(d.spec) + plane;
+  HZ_GLB cpx<T>* out = glb(reinterpret_cast<cpx<T>*>(d.spec)) + plane;
   const cpx<double> t1 = tw1[h1];
   for (int e = threadIdx.x; e < TX * N3; e += kThreads) {
     const int l3 = fdiv(e, zg.rTX), col = e - l3 * TX;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ desc
       e6[4] = scale(G[0][2] + G[2][0], 0.5);
       e6[5] = scale(G[0][1] + G[1][0], 0.5);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) out[(t * 6 + c) * zg.S + o] = fr64<T>(e6[c]);
+      for (int c = 0; c < 6; ++c) gst(out + (t * 6 + c) * zg.S + o, fr64<T>(e6[c]));
     }
   }
 }
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ des
   cpx<T>* twl = buf + yg.TX * N2;
   for (int i = threadIdx.x; i < N2; i += kThreads) twl[i] = tw2T[i];
   const LdsAcc<T> lds{buf, N2, 1};
-  const GblAcc<T> g{reinterpret_cast<cpx<T>*>(d.spec) + t0 * N2, N2, 1, 0, 1};
+  const GblAcc<T> g{glb(reinterpret_cast<cpx<T>*>(d.spec)) + t0 * N2, N2, 1, 0, 1};
   fft_lines<T, emax<T>(), INV>(*plan2, lines, 0.f, true, twl, 1, lds, g, g);
 }
 
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ des
 // sigma = C:(Ebar + deps) in tensor comps (11,22,33,23,13,12); C as an engineering
 // Voigt matrix stored as its upper triangle (21 of 24 slots) row by row
 template <typename T>
-__device__ __forceinline__ void constitutive(const T* __restrict__ Cp, const double* Eb, const T (&de)[6],
+__device__ __forceinline__ void constitutive(const HZ_GLB T* __restrict__ Cp, const double* Eb, const T (&de)[6],
                                              T (&s)[6]) {
   T g[6];
 #pragma unroll
@@ -220,7 +220,7 @@ __device__ __forceinline__ void constitutive(const T* __restrict__ Cp, const dou
   T Cu[24];
 #pragma unroll
   for (int i = 0; i < 24; i += 2) {
-    const cpx<T> v = reinterpret_cast<const cpx<T>*>(Cp)[i / 2];
+    const cpx<T> v = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(Cp) + i / 2);
     Cu[i] = v.x;
     Cu[i + 1] = v.y;
   }
@@ -269,16 +269,16 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
   const int TY = xg.TY, H1p = xg.H1p, M = xg.M;
   const long long N3N2 = (long long)xg.N3 * xg.N2;
   const long long rowoff = (long long)l3 * xg.N2 + l2_0;
-  const T* C = sizeof(T) == 8 ? reinterpret_cast<const T*>(d.C64) : reinterpret_cast<const T*>(d.C32);
-  const uint16_t* ph = d.phase + ((long long)l3 * xg.N2 + l2_0) * xg.N1;
+  const HZ_GLB T* C = glb(sizeof(T) == 8 ? reinterpret_cast<const T*>(d.C64) : reinterpret_cast<const T*>(d.C32));
+  const HZ_GLB uint16_t* ph = glb(d.phase) + ((long long)l3 * xg.N2 + l2_0) * xg.N1;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);  // 6*TY lines of M (pitch H1p)
   cpx<T>* twl = buf + 6 * TY * H1p;
   for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
   const int kh = M / 2 + 1;             // (k, M-k) pairs per line, k = 0..M/2
   const int npair = 6 * kh * TY;
   const LdsAcc<T> lds{buf, H1p, 1};
-  const cpx<T>* src = reinterpret_cast<const cpx<T>*>(d.spec) + (long long)half * 6 * xg.S + rowoff;
-  cpx<T>* dst = reinterpret_cast<cpx<T>*>(d.spec) + (long long)half * 6 * xg.S + rowoff;
+  const HZ_GLB cpx<T>* src = glb(reinterpret_cast<const cpx<T>*>(d.spec)) + (long long)half * 6 * xg.S + rowoff;
+  HZ_GLB cpx<T>* dst = glb(reinterpret_cast<cpx<T>*>(d.spec)) + (long long)half * 6 * xg.S + rowoff;
 
   // 1) load half-spectrum pairs X[k], X[M-k] of each row and apply the C2R split
   //    Z[k] = X[k] + conj(X[M-k]) + i w^k (X[k] - conj(X[M-k])),  w = exp(2 pi i / N1)
@@ -291,9 +291,9 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
       const int p = min(p0 + (int)threadIdx.x + i * kThreads, npair - 1);
       const int q = fdiv(p, xg.rTY), r = p - q * TY;
       const int c = fdiv(q, xg.rKH), kk = q - c * kh;
-      const cpx<T>* s = src + c * xg.S + r;
-      xa[i] = s[kk * N3N2];
-      xb[i] = s[(M - kk) * N3N2];
+      const HZ_GLB cpx<T>* s = src + c * xg.S + r;
+      xa[i] = gld(s + kk * N3N2);
+      xb[i] = gld(s + (M - kk) * N3N2);
     }
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
     }
     const int pa = ph[r * xg.N1 + 2 * n], pb = ph[r * xg.N1 + 2 * n + 1];
     if (d.iso) {
-      const cpx<T> la = reinterpret_cast<const cpx<T>*>(C)[pa], lb = reinterpret_cast<const cpx<T>*>(C)[pb];
+      const cpx<T> la = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + pa), lb = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + pb);
       constitutive_iso<T>(la.x, la.y, d.Ebar, ea, sa);
       constitutive_iso<T>(lb.x, lb.y, d.Ebar, eb, sb);
     } else {
@@ -372,17 +372,304 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
     const int q = fdiv(p, xg.rTY), r = p - q * TY;
     const int c = fdiv(q, xg.rKH), kk = q - c * kh;
     const cpx<T>* Z = buf + (c * TY + r) * H1p;
-    cpx<T>* o = dst + c * xg.S + r;
+    HZ_GLB cpx<T>* o = dst + c * xg.S + r;
     if (kk == 0) {
       const cpx<T> z = Z[0];
-      o[0] = cpx<T>{(z.x + z.y) * sN, (T)0};
-      o[M * N3N2] = cpx<T>{(z.x - z.y) * sN, (T)0};
+      gst(o, cpx<T>{(z.x + z.y) * sN, (T)0});
+      gst(o + M * N3N2, cpx<T>{(z.x - z.y) * sN, (T)0});
     } else {
       const int k2 = M - kk;
       const cpx<T> a = Z[kk], b = Z[k2];
-      o[kk * N3N2] = scale((a + conjg(b)) - mul_i(twN1[kk] * (a - conjg(b))), hs);
-      if (k2 != kk) o[k2 * N3N2] = scale((b + conjg(a)) - mul_i(twN1[k2] * (b - conjg(a))), hs);
+      gst(o + kk * N3N2, scale((a + conjg(b)) - mul_i(twN1[kk] * (a - conjg(b))), hs));
+      if (k2 != kk) gst(o + k2 * N3N2, scale((b + conjg(a)) - mul_i(twN1[k2] * (b - conjg(a))), hs));
     }
+  }
+  block_sum<6>(acc, red);
+  if (threadIdx.x == 0) {
+    double* pp = d.part_sig + (long long)(xg.half >= 0 ? 2 * tile + half : tile) * 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) pp[c] = acc[c];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// P3, fused form (every iteration wherever M = N1/2 factors as below; the
+// output pass, which writes real-space fields, uses the unfused k_xpass).
+// The length-M transforms use radices r0 .. r_{s-1} (inverse) and the reverse
+// order (forward), with r0 in {16, 8, 4, 2} and r_{s-1} in {5, 4, 3, 2}:
+//  * butterfly j of the first inverse pass reads Z at j + m LR (LR = M/r0); the
+//    C2R split partners M - (j + m LR) are the inputs of butterfly LR - j, so one
+//    thread takes both butterflies and every half-spectrum value is loaded once;
+//  * the last inverse pass writes positions j + m LRm, which are exactly the
+//    inputs of butterfly j of the first forward pass (same radix): the
+//    constitutive law runs in registers between the two, on all 6 components;
+//  * the last forward pass writes Z at j + m LR, and the R2C merge pairs it with
+//    butterfly LR - j again, so the merge feeds the stores.
+// For s = 2 each element goes through LDS twice (write + read) per direction.
+// ----------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ cpx<T> c2r_split(cpx<T> a, cpx<T> b, cpx<T> twk) {
+  // Z[k] = X[k] + conj(X[M-k]) + i w^k (X[k] - conj(X[M-k])),  w^k = conj(exp(-2 pi i k / N1))
+  return (a + conjg(b)) + mul_i(conjg(twk) * (a - conjg(b)));
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> r2c_merge(cpx<T> a, cpx<T> b, cpx<T> twk, T hs) {
+  // X[k] = (Z[k] + conj(Z[M-k]) - i w^-k (Z[k] - conj(Z[M-k]))) / 2, times 1/N (eq. FT)
+  return scale((a + conjg(b)) - mul_i(twk * (a - conjg(b))), hs);
+}
+
+// load + split + first inverse radix pass; writes line positions j*R + m
+template <typename T, int R>
+__device__ __forceinline__ void xf_load(const XGeo& xg, const HZ_GLB cpx<T>* __restrict__ src, cpx<T>* buf,
+                                        const cpx<T>* twl) {
+  const int M = xg.M, LR = M / R, TY = xg.TY, nI = LR / 2 + 1;
+  const int n = 6 * nI * TY;
+  const int hs = xg.N3 * xg.N2;  // stride between h1 planes
+#pragma unroll 1
+  for (int w = threadIdx.x; w < n; w += kThreads) {
+    const int q = fdiv(w, xg.rTY), r = w - q * TY;
+    const int c = fdiv(q, xg.rNI), it = q - c * nI;
+    const HZ_GLB cpx<T>* s = src + c * xg.S + r;
+    cpx<T>* line = buf + (c * TY + r) * xg.H1p;
+    const int j = it, j2 = LR - it;
+    cpx<T> x[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) x[m] = gld(s + (j + m * LR) * hs);
+    if (it == 0) {
+      // positions m LR; partner of m >= 1 is R - m, partner of 0 is the Nyquist value X[M]
+      const cpx<T> xM = gld(s + M * hs);
+      cpx<T> z[R];
+      z[0] = c2r_split(x[0], xM, twl[0]);
+#pragma unroll
+      for (int m = 1; m < R; ++m) z[m] = c2r_split(x[m], x[R - m], twl[m * LR]);
+      Dft<T, R, true>::run(z);
+#pragma unroll
+      for (int m = 0; m < R; ++m) line[m] = z[m];
+    } else if (j2 == j) {
+      // butterfly LR/2 is its own partner: m <-> R-1-m
+#pragma unroll
+      for (int m = 0; m < R / 2; ++m) {
+        const cpx<T> a = x[m], b = x[R - 1 - m];
+        x[m] = c2r_split(a, b, twl[j + m * LR]);
+        x[R - 1 - m] = c2r_split(b, a, twl[j + (R - 1 - m) * LR]);
+      }
+      if (R & 1) x[R / 2] = c2r_split(x[R / 2], x[R / 2], twl[j + (R / 2) * LR]);
+      Dft<T, R, true>::run(x);
+#pragma unroll
+      for (int m = 0; m < R; ++m) line[j * R + m] = x[m];
+    } else {
+      cpx<T> y[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) y[m] = gld(s + (j2 + m * LR) * hs);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const cpx<T> a = x[m], b = y[R - 1 - m];
+        x[m] = c2r_split(a, b, twl[j + m * LR]);
+        y[R - 1 - m] = c2r_split(b, a, twl[j2 + (R - 1 - m) * LR]);
+      }
+      Dft<T, R, true>::run(x);
+      Dft<T, R, true>::run(y);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        line[j * R + m] = x[m];
+        line[j2 * R + m] = y[m];
+      }
+    }
+  }
+}
+
+// last inverse pass -> constitutive law on the voxel pairs -> first forward pass.
+// Rounds of whole lines, so a round never reads what an earlier round wrote.
+template <typename T, bool ISO, int R>
+__device__ __forceinline__ void xf_middle(const Desc& d, const XGeo& xg, cpx<T>* buf, const cpx<T>* twl,
+                                          const HZ_GLB uint16_t* __restrict__ ph, double (&acc)[6]) {
+  const int M = xg.M, LR = M / R, TY = xg.TY, H1p = xg.H1p;
+  const int n = TY * LR;
+  const int per = (kThreads / LR) * LR;
+  const HZ_GLB T* C = glb(sizeof(T) == 8 ? reinterpret_cast<const T*>(d.C64) : reinterpret_cast<const T*>(d.C32));
+#pragma unroll 1
+  for (int w0 = 0; w0 < n; w0 += per) {
+    const int w = w0 + (int)threadIdx.x;
+    const bool act = (int)threadIdx.x < per && w < n;
+    cpx<T> z[6][R];
+    int r = 0, j = 0;
+    if (act) {
+      r = fdiv(w, xg.rLRm);
+      j = w - r * LR;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const cpx<T>* line = buf + (c * TY + r) * H1p + j;
+#pragma unroll
+        for (int m = 0; m < R; ++m) z[c][m] = line[m * LR];
+      }
+      // twiddles of the last inverse pass: exp(+2 pi i m j / M) = conj(tw[2 m j])
+#pragma unroll
+      for (int m = 1; m < R; ++m) {
+        const cpx<T> t = conjg(twl[2 * m * j]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) z[c][m] = z[c][m] * t;
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Dft<T, R, true>::run(z[c]);
+      // z[c][m] = eps(2n) + i eps(2n+1), n = j + m LR
+      const HZ_GLB uint32_t* ph2 = reinterpret_cast<const HZ_GLB uint32_t*>(ph + (long long)r * xg.N1);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        __builtin_amdgcn_sched_barrier(0);  // keeps the stiffness loads of one position at a time
+        const int nn = j + m * LR;
+        const uint32_t pp = ph2[nn];
+        const int pa = (int)(pp & 0xffffu), pb = (int)(pp >> 16);
+        T ea[6], eb[6], sa[6], sb[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          ea[c] = z[c][m].x;
+          eb[c] = z[c][m].y;
+        }
+        if (ISO) {
+          const cpx<T> la = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + pa), lb = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + pb);
+          constitutive_iso<T>(la.x, la.y, d.Ebar, ea, sa);
+          constitutive_iso<T>(lb.x, lb.y, d.Ebar, eb, sb);
+        } else {
+          constitutive<T>(C + pa * 24, d.Ebar, ea, sa);
+          __builtin_amdgcn_sched_barrier(0);  // one stiffness row set live at a time
+          constitutive<T>(C + pb * 24, d.Ebar, eb, sb);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          acc[c] += 0.5 * ((double)sa[c] + (double)sb[c]);
+          z[c][m] = cpx<T>{sa[c], sb[c]};
+        }
+      }
+      // first forward pass (no twiddles): outputs at j*R + m
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Dft<T, R, false>::run(z[c]);
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        cpx<T>* line = buf + (c * TY + r) * H1p + j * R;
+#pragma unroll
+        for (int m = 0; m < R; ++m) line[m] = z[c][m];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// last forward pass + R2C merge + stores (with the 1/N of eq. FT)
+template <typename T, int R>
+__device__ __forceinline__ void xf_store(const XGeo& xg, HZ_GLB cpx<T>* __restrict__ dst, const cpx<T>* buf,
+                                         const cpx<T>* twl) {
+  const int M = xg.M, LR = M / R, TY = xg.TY, nI = LR / 2 + 1;
+  const int n = 6 * nI * TY;
+  const int hs = xg.N3 * xg.N2;
+  const T hN = (T)(0.5 * xg.invN), sN = (T)xg.invN;
+#pragma unroll 1
+  for (int w = threadIdx.x; w < n; w += kThreads) {
+    const int q = fdiv(w, xg.rTY), r = w - q * TY;
+    const int c = fdiv(q, xg.rNI), it = q - c * nI;
+    const cpx<T>* line = buf + (c * TY + r) * xg.H1p;
+    HZ_GLB cpx<T>* o = dst + c * xg.S + r;
+    const int j = it, j2 = LR - it;
+    cpx<T> x[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) x[m] = line[j + m * LR];
+    if (it != 0) {
+#pragma unroll
+      for (int m = 1; m < R; ++m) x[m] = x[m] * twl[2 * m * j];
+    }
+    Dft<T, R, false>::run(x);
+    if (it == 0) {
+      gst(o, cpx<T>{(x[0].x + x[0].y) * sN, (T)0});
+      gst(o + M * hs, cpx<T>{(x[0].x - x[0].y) * sN, (T)0});
+#pragma unroll
+      for (int m = 1; m < R; ++m) gst(o + m * LR * hs, r2c_merge(x[m], x[R - m], twl[m * LR], hN));
+    } else if (j2 == j) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) gst(o + (j + m * LR) * hs, r2c_merge(x[m], x[R - 1 - m], twl[j + m * LR], hN));
+    } else {
+      cpx<T> y[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) y[m] = line[j2 + m * LR];
+#pragma unroll
+      for (int m = 1; m < R; ++m) y[m] = y[m] * twl[2 * m * j2];
+      Dft<T, R, false>::run(y);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        gst(o + (j + m * LR) * hs, r2c_merge(x[m], y[R - 1 - m], twl[j + m * LR], hN));
+        gst(o + (j2 + m * LR) * hs, r2c_merge(y[m], x[R - 1 - m], twl[j2 + m * LR], hN));
+      }
+    }
+  }
+}
+
+// ISO: every phase of the material is isotropic (separate instantiations keep the
+// register budget of each at two waves per SIMD in FP64)
+template <typename T, bool ISO>
+__global__ __launch_bounds__(kThreads) void k_xfused(const Desc* __restrict__ descs,
+                                                     const int* __restrict__ active, XGeo xg,
+                                                     const Plan* __restrict__ planXi,
+                                                     const Plan* __restrict__ planXf,
+                                                     const cpx<T>* __restrict__ twN1) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[6 * 4];
+  const Desc& d = descs[active[blockIdx.y]];
+  if (problem_done(d) || (d.iso != 0) != ISO) return;
+  const int tiles2 = xg.N2 / xg.TY;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int half = xg.half >= 0 ? xg.half : (tile & 1);
+  const int rt = xg.half >= 0 ? tile : (tile >> 1);
+  const int l3 = rt / tiles2;
+  const int l2_0 = (rt % tiles2) * xg.TY;
+  const int TY = xg.TY, M = xg.M;
+  const long long row0 = (long long)l3 * xg.N2 + l2_0;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* twl = buf + 6 * TY * xg.H1p;
+  for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
+  __syncthreads();
+  const int off = (int)(half * 6 * xg.S + row0);
+  const HZ_GLB cpx<T>* src = glb(reinterpret_cast<const cpx<T>*>(d.spec)) + off;
+  HZ_GLB cpx<T>* dst = glb(reinterpret_cast<cpx<T>*>(d.spec)) + off;
+  const Plan& pi = *planXi;
+  const Plan& pf = *planXf;
+  const int np = pi.np;
+  switch (pi.radix[0]) {
+    case 16: xf_load<T, 16>(xg, src, buf, twl); break;
+    case 8: xf_load<T, 8>(xg, src, buf, twl); break;
+    case 4: xf_load<T, 4>(xg, src, buf, twl); break;
+    default: xf_load<T, 2>(xg, src, buf, twl); break;
+  }
+  __syncthreads();
+  const LdsAcc<T> lds{buf, xg.H1p, 1};
+  int Ns = pi.radix[0];
+#pragma unroll 1
+  for (int p = 1; p < np - 1; ++p) {
+    pass_any<T, emax<T>(), true>(pi.radix[p], M, Ns, 6 * TY, true, twl, 2, lds, lds, true, pi.rLR[p], pi.rNs[p], 0.f);
+    __syncthreads();
+    Ns *= pi.radix[p];
+  }
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const HZ_GLB uint16_t* ph = glb(d.phase) + row0 * xg.N1;
+  switch (pi.radix[np - 1]) {
+    case 4: xf_middle<T, ISO, 4>(d, xg, buf, twl, ph, acc); break;
+    case 2: xf_middle<T, ISO, 2>(d, xg, buf, twl, ph, acc); break;
+    case 5: xf_middle<T, ISO, 5>(d, xg, buf, twl, ph, acc); break;
+    default: xf_middle<T, ISO, 3>(d, xg, buf, twl, ph, acc); break;
+  }
+  Ns = pf.radix[0];
+#pragma unroll 1
+  for (int p = 1; p < np - 1; ++p) {
+    pass_any<T, emax<T>(), false>(pf.radix[p], M, Ns, 6 * TY, true, twl, 2, lds, lds, true, pf.rLR[p], pf.rNs[p], 0.f);
+    __syncthreads();
+    Ns *= pf.radix[p];
+  }
+  switch (pf.radix[np - 1]) {
+    case 16: xf_store<T, 16>(xg, dst, buf, twl); break;
+    case 8: xf_store<T, 8>(xg, dst, buf, twl); break;
+    case 4: xf_store<T, 4>(xg, dst, buf, twl); break;
+    default: xf_store<T, 2>(xg, dst, buf, twl); break;
   }
   block_sum<6>(acc, red);
   if (threadIdx.x == 0) {
@@ -431,7 +718,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
   for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
   const long long plane = (long long)h1 * N3 * N2 + h2_0;
   const LdsAcc<T> lds{buf, 1, lines};
-  const cpx<T>* sp = reinterpret_cast<const cpx<T>*>(d.spec) + plane;
+  const HZ_GLB cpx<T>* sp = glb(reinterpret_cast<const cpx<T>*>(d.spec)) + plane;
   const cpx<double> t1 = tw1[h1];
   // phase A: each thread walks a run of l3 values of one column downwards, so that
   // R(l) = A(l) + B(l+1) needs one extra row of loads per run, not one per element
@@ -456,8 +743,8 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
         cpx<T> s1[6], s2[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-          s1[c] = sp[c * zg.S + o];
-          s2[c] = sp[(6 + c) * zg.S + o];
+          s1[c] = gld(sp + c * zg.S + o);
+          s2[c] = gld(sp + (6 + c) * zg.S + o);
         }
         cpx<double> y1[3], y2[3];
         sig_dot(s1, b1, y1);
@@ -472,8 +759,8 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
           cpx<T> s1[6], s2[6];
 #pragma unroll
           for (int c = 0; c < 6; ++c) {
-            s1[c] = sp[c * zg.S + o];
-            s2[c] = sp[(6 + c) * zg.S + o];
+            s1[c] = gld(sp + c * zg.S + o);
+            s2[c] = gld(sp + (6 + c) * zg.S + o);
           }
           cpx<double> x1[3], x2[3], y1[3], y2[3];
           sig_dot(s1, a1, x1);
@@ -505,13 +792,13 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
     const int MODE = d.cmode;
     if (MODE == 2) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) r[c] = r[c] + to64(reinterpret_cast<const cpx<float>*>(d.r32)[c * zg.S + plane + o]);
+      for (int c = 0; c < 3; ++c) r[c] = r[c] + to64(gld(glb(reinterpret_cast<const cpx<float>*>(d.r32)) + c * zg.S + plane + o));
     }
     part[0] += 0.25 * w * (r[0].x * r[0].x + r[0].y * r[0].y + r[1].x * r[1].x + r[1].y * r[1].y +
                            r[2].x * r[2].x + r[2].y * r[2].y);
     if (MODE == 1) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) reinterpret_cast<cpx<float>*>(d.r32)[c * zg.S + plane + o] = fr64<float>(r[c]);
+      for (int c = 0; c < 3; ++c) gst(glb(reinterpret_cast<cpx<float>*>(d.r32)) + c * zg.S + plane + o, fr64<float>(r[c]));
       continue;
     }
     cpx<double> D1[3], D2[3];
@@ -557,13 +844,13 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
                             {a01 * inv, a11 * inv, a12 * inv},
                             {a02 * inv, a12 * inv, a22 * inv}};
     const int p = cur_slot(d);
-    const cpx<T>* uin = reinterpret_cast<const cpx<T>*>(d.u[p]) + plane;
-    cpx<T>* uout = reinterpret_cast<cpx<T>*>(d.u[1 - p]) + plane;
+    const HZ_GLB cpx<T>* uin = glb(reinterpret_cast<const cpx<T>*>(d.u[p])) + plane;
+    HZ_GLB cpx<T>* uout = glb(reinterpret_cast<cpx<T>*>(d.u[1 - p])) + plane;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const cpx<double> dw = {O[i][0] * r[0].x + O[i][1] * r[1].x + O[i][2] * r[2].x,
                               O[i][0] * r[0].y + O[i][1] * r[1].y + O[i][2] * r[2].y};
-      uout[i * zg.S + o] = fr64<T>(to64(uin[i * zg.S + o]) - dw);
+      gst(uout + i * zg.S + o, fr64<T>(to64(gld(uin + i * zg.S + o)) - dw));
     }
   }
   block_sum<1>(part, red);
@@ -729,6 +1016,20 @@ hipError_t launch_xpass(const Desc* descs, const int* active, int nact, const XG
 }
 
 template <typename T>
+hipError_t launch_xfused(const Desc* descs, const int* active, int nact, bool iso, const XGeo& xg,
+                         const Plan* planXi, const Plan* planXf, const void* twN1, hipStream_t s) {
+  const size_t shm = ((size_t)6 * xg.TY * xg.H1p + xg.N1) * sizeof(cpx<T>);
+  dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY) * (xg.half >= 0 ? 1 : 2)), nact);
+  if (iso)
+    hipLaunchKernelGGL((k_xfused<T, true>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf,
+                       (const cpx<T>*)twN1);
+  else
+    hipLaunchKernelGGL((k_xfused<T, false>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf,
+                       (const cpx<T>*)twN1);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_zcon(const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
                        const void* tw3T, const void* tw1, const void* tw2, const void* tw3, hipStream_t s) {
   const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
@@ -764,6 +1065,8 @@ template hipError_t launch_yline<double>(const Desc*, const int*, int, const YGe
 template hipError_t launch_yline<float>(const Desc*, const int*, int, const YGeo&, const Plan*, const void*, bool, hipStream_t);
 template hipError_t launch_xpass<double>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
 template hipError_t launch_xpass<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xfused<double>(const Desc*, const int*, int, bool, const XGeo&, const Plan*, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xfused<float>(const Desc*, const int*, int, bool, const XGeo&, const Plan*, const Plan*, const void*, hipStream_t);
 template hipError_t launch_zcon<double>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
 template hipError_t launch_zcon<float>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
 
