@@ -5,8 +5,11 @@ Workload (the headline configuration): 128^3 periodic cell, Boolean model of
 overlapping spheres (radius 8, seeded, 30% volume fraction), stiffness
 contrast 1e3 (nu = 0.3), all six unit macroscopic strains solved as one batch
 in FP64 (the effective-stiffness computation).  A "step" is one iteration of
-Algorithm 1 over all six loads: expand, six 1D FFT passes, constitutive law,
-Green-operator update and FP64 residual reduction.
+Algorithm 1 over all six loads.  The default realisation is the stencil form
+(transforms of the 3 displacement components, real-space strains, constitutive
+law and corner forces, transforms of the 3 force components, Green-operator
+update, FP64 residual reduction); the Fourier form (12 strain/stress fields
+through the transforms) is timed beside it for context.
 
 Prints ONE JSON line:
   value          voxel-iterations/s (128^3 voxels x 6 loads x steps / timed seconds)
@@ -48,20 +51,37 @@ def source_digest():
 
 
 def kernel_bytes(kind, S, N, nloads, csz):
-    """Algorithmic HBM bytes of one launch of a pass over `nloads` problems:
-    complex spectra moved (S complex elements per component, csz bytes each)."""
-    units = {
-        "zexpand": 3 + 12,         # read u (3), write 12 strain spectra
-        "yinv": 24, "yfwd": 24,    # read 12, write 12
-        "xpass": 24,               # read 12, write 12 (+ phase map)
-        "zcontract": 12 + 3 + 3,   # read 12 stress spectra + u, write u
+    """Algorithmic HBM bytes of one launch of a pass over `nloads` problems: complex
+    spectra (S complex elements per field, csz bytes each) and real fields (N values,
+    csz/2 bytes each) each read or written once, plus the uint16 phase map."""
+    rsz = csz // 2
+    spectral = {                         # Fourier form: 12 strain/stress fields
+        "zexpand": 15 * S * csz,         # read u (3), write 12 strain spectra
+        "yinv": 24 * S * csz,            # read 12, write 12
+        "yfwd": 24 * S * csz,
+        "xpass": 24 * S * csz + 2 * N,   # read 12, write 12, phase map
+        "zcontract": 18 * S * csz,       # read 12 stress spectra + u, write u
     }
-    if kind not in units:
+    stencil = {                          # stencil form: 3 displacement / force fields
+        "zexpand3": 6 * S * csz,         # read u, write 3 fields
+        "yinv3": 6 * S * csz,
+        "xc2r": 3 * S * csz + 3 * N * rsz,
+        "stencil": 6 * N * rsz + 2 * N,  # read u (corners), write g, phase map
+        "xr2c": 3 * N * rsz + 3 * S * csz,
+        "yfwd3": 6 * S * csz,
+        "zcontract3": 9 * S * csz,       # read g and u, write u
+    }
+    table = {**spectral, **stencil}
+    if kind not in table:
         return None
-    b = units[kind] * S * csz
-    if kind == "xpass":
-        b += 2 * N
-    return b * nloads
+    return table[kind] * nloads
+
+
+def iteration_bytes(scheme, S, N, csz):
+    """Algorithmic bytes of one iteration of one load (sum over its passes)."""
+    kinds = (["zexpand", "yinv", "xpass", "yfwd", "zcontract"] if scheme == "spectral" else
+             ["zexpand3", "yinv3", "xc2r", "stencil", "xr2c", "yfwd3", "zcontract3"])
+    return sum(kernel_bytes(k, S, N, 1, csz) for k in kinds)
 
 
 def cpu_baseline(problem, max_seconds=25.0):
@@ -219,6 +239,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-6 comparison")
     ap.add_argument("--ttt-n", type=int, default=256, help="grid size of the time-to-1e-6 polycrystal")
+    ap.add_argument("--scheme", choices=["auto", "spectral", "stencil"], default="auto")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-n", type=int, default=64, help="requests in the serving stream")
     ap.add_argument("--serve-max-iters", type=int, default=1000, help="iteration budget per served request")
@@ -255,14 +276,16 @@ def main():
     g.bind(hz.HZ_FP64, 6)
     torch.cuda.synchronize()
 
+    schemes = {"auto": hz.HZ_SCHEME_AUTO, "spectral": hz.HZ_SCHEME_SPECTRAL, "stencil": hz.HZ_SCHEME_STENCIL}
+    sch = schemes[a.scheme]
     # warmup, then exactly `steps` iterations of all six loads
     if a.warmup > 0:
-        g.solve(p.loads, C0=p.C0, fixed_iters=a.warmup - 1, check_every=1 << 20)
+        g.solve(p.loads, C0=p.C0, fixed_iters=a.warmup - 1, check_every=1 << 20, scheme=sch)
     torch.cuda.synchronize()
     g.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = g.solve(p.loads, C0=p.C0, fixed_iters=a.steps - 1, check_every=1 << 20)
+    r = g.solve(p.loads, C0=p.C0, fixed_iters=a.steps - 1, check_every=1 << 20, scheme=sch)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     g.profile(False)
@@ -270,6 +293,19 @@ def main():
     assert np.all(r.iters == a.steps - 1)
     value = N * 6 * a.steps / dt
     log(f"bench: {a.steps} steps in {dt * 1e3:.1f} ms -> {value / 1e9:.3f} G voxel-iters/s")
+    # the other realisation, same workload, for context (not the headline value)
+    other = hz.HZ_SCHEME_SPECTRAL if any(k.startswith("stencil") for k in prof) else hz.HZ_SCHEME_STENCIL
+    alt = None
+    if g.scheme_available(other):
+        k2 = max(4, a.steps // 4)
+        g.solve(p.loads, C0=p.C0, fixed_iters=1, check_every=1 << 20, scheme=other)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.solve(p.loads, C0=p.C0, fixed_iters=k2 - 1, check_every=1 << 20, scheme=other)
+        torch.cuda.synchronize()
+        alt = {"scheme": "spectral" if other == hz.HZ_SCHEME_SPECTRAL else "stencil", "steps": k2,
+               "voxel_iters_per_s": N * 6 * k2 / (time.perf_counter() - t1)}
+        log(f"bench: other scheme {alt}")
 
     # roofline of the dominant kernel from the library's HIP events on its stream
     kinds = {}
@@ -294,8 +330,9 @@ def main():
             "avg_launch_ms": round(avg_s * 1e3, 4), "launches": cnt}
     per_kernel = {k: {"ms_per_launch": round(v[2] / v[3], 4), "share": round(v[2] / sum(x[2] for x in kinds.values()), 3)}
                   for k, v in kinds.items()}
-    # whole-iteration fraction against the 105-unit byte model of one iteration
-    model_bytes = (105 * S * 16 + 2 * N) / N
+    # whole-iteration fraction: algorithmic bytes of one iteration of the scheme used
+    scheme = "stencil" if any(k.startswith("stencil") for k in prof) else "spectral"
+    model_bytes = iteration_bytes(scheme, S, N, 16) / N
     iter_frac = value * model_bytes / (HBM_PEAK_GBS * 1e9)
 
     ttt = None
@@ -323,7 +360,8 @@ def main():
         "config": {"workload": f"boolean{N1}_contrast1e3_6loads", "grid": [N1, N2, N3], "loads": 6,
                    "precision": "fp64", "vf": round(p.info["vf"], 4), "n_spheres": p.info["n_spheres"],
                    "parallelism": "single GPU"},
-        "roofline": roof, "iteration_roofline_frac_105unit_model": round(iter_frac, 4),
+        "roofline": roof, "scheme": scheme, "other_scheme": alt, "bytes_per_voxel_iteration": round(model_bytes, 1),
+        "iteration_roofline_frac": round(iter_frac, 4),
         "per_kernel": per_kernel, "cpu_baseline": cpu, "time_to_1e-6": ttt, "serving": serving,
     }
     print(json.dumps(out), flush=True)

@@ -68,6 +68,18 @@ typedef struct hz_grid_s* hz_grid;
 #define HZ_FP64 0
 #define HZ_FP32_REFINE 1
 
+/* Realisation of the iteration; both give the same iterates (eq. Dq is the
+ * Fourier symbol of the real-space stencils of eqs. DA1-DA2).
+ * HZ_SCHEME_SPECTRAL: Algorithm 1 as written, the 12 strain/stress components
+ *   through the transforms.
+ * HZ_SCHEME_STENCIL: strains and corner forces by the 4-corner stencils in real
+ *   space, so only the 3 displacement and 3 force components are transformed
+ *   (needs N1/2 with a power-of-two factor, see hz_scheme_available).
+ * HZ_SCHEME_AUTO: the stencil form where available, else the spectral one. */
+#define HZ_SCHEME_AUTO 0
+#define HZ_SCHEME_SPECTRAL 1
+#define HZ_SCHEME_STENCIL 2
+
 typedef struct {
   double tol;               /* stop at the first iterate k with eps_k < tol (eq. tolerance)   */
   int32_t max_iters;        /* cap on updates (FP64) or on FP32 inner updates (refinement)     */
@@ -80,6 +92,7 @@ typedef struct {
   double* trace_mean;       /* optional [n_loads][max_iters+1][6]: <sigma>_k                    */
   double inner_rho;         /* refinement: inner loop stops at rho * eps of its FP64 sweep      */
   int32_t inner_max;        /* refinement: cap on inner iterations per outer round              */
+  int32_t scheme;           /* HZ_SCHEME_AUTO, HZ_SCHEME_SPECTRAL or HZ_SCHEME_STENCIL           */
 } hz_opts;
 
 typedef struct {
@@ -95,7 +108,8 @@ typedef struct {
 } hz_info;
 
 /* Fill *o with defaults: tol 1e-8, max_iters 2000, HZ_FP64, automatic reference,
- * fixed_iters -1, check_every 8, no traces, inner_rho 1e-3, inner_max 400. */
+ * fixed_iters -1, check_every 8, no traces, inner_rho 1e-3, inner_max 400,
+ * HZ_SCHEME_AUTO. */
 void hz_default_opts(hz_opts* o);
 
 /* Create a grid handle for an n1 x n2 x n3 periodic cell (Sec. 2.1).
@@ -138,6 +152,11 @@ int hz_effective_stiffness(hz_grid g, const hz_opts* o, double C_eff[36], hz_inf
  * out[3][n1/2+1][n3][n2] complex (interleaved re,im) FP64, in the library's phase
  * convention u~(q) = exp(i q.(1/2,1/2,1/2)) u(q) (u(q) of eq. FT_u). */
 int hz_get_displacement(hz_grid g, int32_t load, double* out);
+
+/* 1 if the grid's sizes allow the given scheme (HZ_SCHEME_SPECTRAL: always;
+ * HZ_SCHEME_STENCIL: N1/2 factors with a power-of-two first radix), 0 if not,
+ * negative error code on invalid arguments. */
+int hz_scheme_available(hz_grid g, int32_t scheme);
 
 /* Reference medium the automatic rule picks for a set of phases: isotropic with
  * nu0 = 0 and Mandel modulus at the midpoint of the smallest and largest Mandel

@@ -14,8 +14,8 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (HZ_EDIVERGED, HZ_FP32_REFINE, HZ_FP64, HZ_NOT_CONVERGED, HZ_OK, HZ_PENDING, HZ_STAGNATED,
-                   HzError, check, hz_info, hz_opts)
+from ._abi import (HZ_EDIVERGED, HZ_FP32_REFINE, HZ_FP64, HZ_NOT_CONVERGED, HZ_OK, HZ_PENDING, HZ_SCHEME_AUTO,
+                   HZ_SCHEME_SPECTRAL, HZ_SCHEME_STENCIL, HZ_STAGNATED, HzError, check, hz_info, hz_opts)
 
 __all__ = ["Grid", "Server", "SolveResult", "HZ_FP64", "HZ_FP32_REFINE", "HzError", "reference_medium", "lib"]
 
@@ -37,7 +37,7 @@ def reference_medium(C):
 
 
 def _opts(tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1, check_every=8, inner_rho=1e-3,
-          inner_max=400):
+          inner_max=400, scheme=HZ_SCHEME_AUTO):
     o = hz_opts()
     lib().hz_default_opts(ctypes.byref(o))
     o.tol = tol
@@ -47,6 +47,7 @@ def _opts(tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1, 
     o.check_every = check_every
     o.inner_rho = inner_rho
     o.inner_max = inner_max
+    o.scheme = scheme
     if C0 is not None:
         o.ref_mode = 1
         o.ref_C[:] = np.asarray(C0, dtype=np.float64).reshape(36).tolist()
@@ -140,11 +141,12 @@ class Grid:
 
     # -- solve -----------------------------------------------------------------
     def solve(self, E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1,
-              fields=False, trace=False, check_every=8, inner_rho=1e-3, inner_max=400) -> SolveResult:
+              fields=False, trace=False, check_every=8, inner_rho=1e-3, inner_max=400,
+              scheme=HZ_SCHEME_AUTO) -> SolveResult:
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
         nl = E.shape[0]
         self._ensure(precision, nl)
-        o = _opts(tol, max_iters, precision, C0, fixed_iters, check_every, inner_rho, inner_max)
+        o = _opts(tol, max_iters, precision, C0, fixed_iters, check_every, inner_rho, inner_max, scheme)
         T = (fixed_iters if fixed_iters >= 0 else max_iters) + 1
         tr = tm = None
         if trace:
@@ -170,6 +172,9 @@ class Grid:
             E[J, J] = 1.0 if J < 3 else 0.5
         r = self.solve(E, tol=tol, max_iters=max_iters, precision=precision, C0=C0, **kw)
         return r.mean_sigma.T.copy(), r
+
+    def scheme_available(self, scheme) -> bool:
+        return bool(check(lib().hz_scheme_available(self._h, scheme)))
 
     def displacement(self, load=0):
         """u~(q) of the reported iterate: complex [3, N1/2+1, N3, N2] (library phase convention)."""
@@ -225,9 +230,9 @@ class Server:
             self._h = None
 
     def submit(self, grid: "Grid", E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, inner_rho=1e-3,
-               inner_max=400) -> int:
+               inner_max=400, scheme=HZ_SCHEME_AUTO) -> int:
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
-        o = _opts(tol, max_iters, precision, C0, -1, 8, inner_rho, inner_max)
+        o = _opts(tol, max_iters, precision, C0, -1, 8, inner_rho, inner_max, scheme)
         rid = ctypes.c_int64()
         check(lib().hz_server_submit(self._h, grid._h, E.shape[0], _dptr(E), ctypes.byref(o), ctypes.byref(rid)))
         self._nloads[rid.value] = E.shape[0]

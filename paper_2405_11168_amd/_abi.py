@@ -21,6 +21,10 @@ HZ_EDIVERGED = -7
 HZ_FP64 = 0
 HZ_FP32_REFINE = 1
 
+HZ_SCHEME_AUTO = 0
+HZ_SCHEME_SPECTRAL = 1
+HZ_SCHEME_STENCIL = 2
+
 
 class hz_opts(ctypes.Structure):
     _fields_ = [
@@ -35,6 +39,7 @@ class hz_opts(ctypes.Structure):
         ("trace_mean", POINTER(c_double)),
         ("inner_rho", c_double),
         ("inner_max", c_int32),
+        ("scheme", c_int32),
     ]
 
 
@@ -63,6 +68,7 @@ SIGNATURES = {
     "hz_effective_stiffness": (c_int32, [c_void_p, POINTER(hz_opts), POINTER(c_double), POINTER(hz_info)]),
     "hz_get_displacement": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "hz_reference_medium": (c_int32, [c_int32, POINTER(c_double), POINTER(c_double)]),
+    "hz_scheme_available": (c_int32, [c_void_p, c_int32]),
     "hz_profile": (c_int32, [c_void_p, c_int32]),
     "hz_profile_read": (c_int32, [c_void_p, c_int32, POINTER(c_char_p), POINTER(c_double), POINTER(c_int64)]),
     "hz_destroy_grid": (None, [c_void_p]),

@@ -37,6 +37,13 @@ void check_opts(const hz_opts& o) {
   if (o.max_iters < 0 || o.max_iters > kTraceCap - 1) fail(HZ_EINVAL, "max_iters out of range [0, 4096]");
   if (o.fixed_iters > kTraceCap - 1) fail(HZ_EINVAL, "fixed_iters out of range");
   if (o.inner_max < 0 || o.inner_max > 100000) fail(HZ_EINVAL, "inner_max out of range");
+  if (o.scheme < HZ_SCHEME_AUTO || o.scheme > HZ_SCHEME_STENCIL) fail(HZ_EINVAL, "unknown scheme");
+}
+
+int pick_form(const Shape& sh, int scheme) {
+  if (scheme == HZ_SCHEME_STENCIL && !sh.stencil) fail(HZ_EINVAL, "the stencil scheme needs N1/2 with a power-of-two factor");
+  if (scheme == HZ_SCHEME_SPECTRAL) return HZ_SCHEME_SPECTRAL;
+  return sh.stencil ? HZ_SCHEME_STENCIL : HZ_SCHEME_SPECTRAL;
 }
 
 void check_loads(const double* E, int n) {
@@ -52,6 +59,7 @@ void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, cons
   p.shape = sh;
   p.tab = tab;
   p.prec = o.precision;
+  p.form = pick_form(*sh, o.scheme);
   for (int c = 0; c < 6; ++c) p.E[c] = E[c];
   p.tol = o.tol;
   p.max_iters = o.max_iters;
@@ -408,6 +416,7 @@ void hz_default_opts(hz_opts* o) {
   o->check_every = 8;
   o->inner_rho = 1e-3;
   o->inner_max = 400;
+  o->scheme = HZ_SCHEME_AUTO;
 }
 
 const char* hz_last_error(void) { return g_err.c_str(); }
@@ -522,6 +531,15 @@ int hz_get_displacement(hz_grid g, int32_t load, double* out) {
   HZ_GUARD_END
 }
 
+int hz_scheme_available(hz_grid g, int32_t scheme) {
+  HZ_GUARD_BEGIN
+  if (!g) fail(HZ_EINVAL, "NULL handle");
+  if (scheme == HZ_SCHEME_SPECTRAL || scheme == HZ_SCHEME_AUTO) return 1;
+  if (scheme == HZ_SCHEME_STENCIL) return g->shape.stencil ? 1 : 0;
+  fail(HZ_EINVAL, "unknown scheme");
+  HZ_GUARD_END
+}
+
 int hz_reference_medium(int32_t n_phases, const double* C_voigt, double C0_out[36]) {
   HZ_GUARD_BEGIN
   if (n_phases <= 0 || !C_voigt || !C0_out) fail(HZ_EINVAL, "bad arguments");
@@ -616,6 +634,7 @@ int hz_server_submit(hz_server s, hz_grid g, int32_t n_loads, const double* E, c
   if (!s || !g || !E || !o || !id || n_loads <= 0) fail(HZ_EINVAL, "bad submit arguments");
   if (!g->mat) fail(HZ_ENOMATERIAL, "material not set");
   check_opts(*o);
+  pick_form(g->shape, o->scheme);
   if (o->precision == HZ_FP64 && o->fixed_iters >= 0) fail(HZ_EINVAL, "fixed_iters is not served");
   check_loads(E, n_loads);
   if (n_loads > s->max_problems) fail(HZ_EWORKSPACE, "more loads than the server has slots");

@@ -30,7 +30,8 @@
 namespace hz {
 
 const char* const kKindNames[K_COUNT] = {"zexpand", "yinv", "xpass", "yfwd", "zcontract", "finalize", "accumulate",
-                                         "zero"};
+                                         "zero", "zexpand3", "yinv3", "xc2r", "stencil", "xr2c", "yfwd3",
+                                         "zcontract3"};
 
 [[noreturn]] void fail(int code, const std::string& m) { throw HzError{code, m}; }
 
@@ -173,7 +174,21 @@ void Shape::init(int n1, int n2, int n3) {
     H1p[d] = hp;
     nbx[d] = 2 * G.N3 * (G.N2 / tyx);
     nbq[d] = G.H1 * (G.N2 / tx);
+    // 3-field x transforms of the stencil form
+    int ty3 = std::min(32, G.N2);
+    auto x3_fits = [&](int t) { return (3 * t * hp + G.N1) * csz <= kLdsBytes && 3 * t * (G.N1 / 2) <= tile; };
+    while (ty3 > 1 && (!x3_fits(ty3) || G.N2 % ty3)) --ty3;
+    TY3[d] = x3_fits(ty3) ? ty3 : 0;
   }
+  stencil = xfused && TY3[0] > 0 && TY3[1] > 0;
+  sg.N1 = G.N1;
+  sg.N2 = G.N2;
+  sg.N3 = G.N3;
+  sg.TZ = std::min(16, G.N3);
+  sg.tx = (G.N1 + kStX - 1) / kStX;
+  sg.ty = (G.N2 + kStY - 1) / kStY;
+  sg.tz = (G.N3 + sg.TZ - 1) / sg.TZ;
+  nbs = sg.tx * sg.ty * sg.tz;
 }
 
 // ---------------------------------------------------------------------------
@@ -497,7 +512,7 @@ void pass_front(Engine& e, const Shape& sh, const ShapeTables& tb, const int* ac
     Launch L(e, K_ZEXP, d);
     L.done(launch_zexp<T>(e.d_desc, act, n, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], e.stream), "z expand");
   }
-  const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3};
+  const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3, 0};
   Launch L(e, K_YINV, d);
   L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], true, e.stream), "y inverse");
 }
@@ -538,14 +553,15 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
   {
-    const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3};
+    const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3, 0};
     Launch L(e, K_YFWD, d);
     L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], false, e.stream), "y forward");
   }
   {
     const ZGeo zg = zgeo(sh, d);
     Launch L(e, K_ZCON, d);
-    L.done(launch_zcon<T>(e.d_desc, act, n, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2], e.stream),
+    L.done(launch_zcon<T>(e.d_desc, act, n, false, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
+                          e.stream),
            "z contract");
   }
   const FinGeo fg{sh.nbx[d], sh.nbq[d], 1.0 / (double)G.N};
@@ -558,6 +574,59 @@ void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
   pass_front<T>(e, sh, tb, act, n);
   pass_x<T>(e, sh, tb, act, n, n_iso, 0);
   pass_back<T>(e, sh, tb, act, n);
+}
+
+// the same iteration in the stencil form: 3-field transforms around the real-space
+// strain / constitutive / corner-force kernel
+template <typename T>
+void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso) {
+  const int d = sizeof(T) == 8;
+  const Geo& G = sh.geo;
+  const char* const* tw = d ? tb.tw64 : tb.tw32;
+  const ZGeo zg = zgeo(sh, d);
+  {
+    Launch L(e, K_ZEXP3, d);
+    L.done(launch_zexp3<T>(e.d_desc, act, n, zg, tb.plans + 2, tw[2], e.stream), "z expand");
+  }
+  {
+    const YGeo yg{G.N2, sh.TXy[d], (long long)3 * G.H1 * G.N3, 0};
+    Launch L(e, K_YINV3, d);
+    L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], true, e.stream), "y inverse");
+  }
+  const int M = G.N1 / 2;
+  XGeo xg{G.N1, G.N2, G.N3, G.H1, sh.H1p[d], sh.TY3[d], M, recip(sh.TY3[d]), recip(M / 2 + 1), recip(M),
+          G.S, 1.0 / (double)G.N, 0, 0, 1.0f, 1.0f};
+  {
+    const Plan& pi = sh.plans[4];
+    xg.rNI = recip(M / pi.radix[0] / 2 + 1);
+    Launch L(e, K_XC2R, d);
+    L.done(launch_xc2r<T>(e.d_desc, act, n, xg, tb.plans + 4, tw[0], e.stream), "x c2r");
+  }
+  {
+    Launch L(e, K_STEN, d);
+    if (n_iso > 0) L.done(launch_stencil<T>(e.d_desc, act, n_iso, true, sh.sg, e.stream), "stencil");
+    if (n > n_iso) L.done(launch_stencil<T>(e.d_desc, act + n_iso, n - n_iso, false, sh.sg, e.stream), "stencil");
+  }
+  {
+    const Plan& pf = sh.plans[5];
+    xg.rNI = recip(M / pf.radix[pf.np - 1] / 2 + 1);
+    Launch L(e, K_XR2C, d);
+    L.done(launch_xr2c<T>(e.d_desc, act, n, xg, tb.plans + 5, tw[0], e.stream), "x r2c");
+  }
+  {
+    const YGeo yg{G.N2, sh.TXy[d], (long long)3 * G.H1 * G.N3, 9 * G.S};
+    Launch L(e, K_YFWD3, d);
+    L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], false, e.stream), "y forward");
+  }
+  {
+    Launch L(e, K_ZCON3, d);
+    L.done(launch_zcon<T>(e.d_desc, act, n, true, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
+                          e.stream),
+           "z contract");
+  }
+  const FinGeo fg{sh.nbs, sh.nbq[d], 1.0 / (double)G.N};
+  Launch L(e, K_FINAL, d);
+  L.done(launch_finalize(e.d_desc, act, n, fg, e.stream), "finalize");
 }
 
 bool kernel_fp64(PState s) { return s == PS_IT64 || s == PS_SWEEP; }
@@ -691,7 +760,7 @@ std::vector<Prob*> Engine::tick() {
   std::vector<Seg> segs;
   auto put = [&](int cat, Prob* p) {
     for (auto& s : segs)
-      if (s.cat == cat && s.proto->tab.plans == p->tab.plans) {
+      if (s.cat == cat && s.proto->tab.plans == p->tab.plans && (cat < 4 || s.proto->form == p->form)) {
         s.ps.push_back(p);
         return;
       }
@@ -768,8 +837,14 @@ std::vector<Prob*> Engine::tick() {
     const int* act = d_active + s.off;
     const int n = (int)s.ps.size();
     for (int i = 0; i < s.K; ++i) {
-      if (s.cat == 4) iteration<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
-      else iteration<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
+      const bool st = s.proto->form == HZ_SCHEME_STENCIL;
+      if (s.cat == 4) {
+        if (st) iteration_stencil<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
+        else iteration<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
+      } else {
+        if (st) iteration_stencil<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
+        else iteration<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
+      }
       hip_check(hipEventRecord(event(nev++), stream), "hipEventRecord");
     }
   }

@@ -25,8 +25,16 @@ template <typename T>
 hipError_t launch_xfused(const Desc*, const int*, int, bool, const XGeo&, const Plan*, const Plan*, const void*,
                          hipStream_t);
 template <typename T>
-hipError_t launch_zcon(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*,
-                       const void*, hipStream_t);
+hipError_t launch_zcon(const Desc*, const int*, int, bool, const ZGeo&, const Plan*, const void*, const void*,
+                       const void*, const void*, hipStream_t);
+template <typename T>
+hipError_t launch_zexp3(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
+template <typename T>
+hipError_t launch_xc2r(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template <typename T>
+hipError_t launch_xr2c(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template <typename T>
+hipError_t launch_stencil(const Desc*, const int*, int, bool, const SGeo&, hipStream_t);
 hipError_t launch_finalize(const Desc*, const int*, int, const FinGeo&, hipStream_t);
 hipError_t launch_accumulate(const Desc*, const int*, int, long long, hipStream_t);
 hipError_t launch_zero(const Desc*, const int*, int, int, long long, hipStream_t);
@@ -53,8 +61,16 @@ struct Shape {
   bool xfused = false;  // the x pass runs in its fused form (needs >= 2 radix passes of N1/2)
   int TXz[2]{}, TXy[2]{}, TYx[2]{}, H1p[2]{};  // [0] FP32 kernels, [1] FP64 kernels
   int nbx[2]{}, nbq[2]{};                      // partial-sum blocks of the x and z passes
+  // stencil form (needs the fused x factorisation)
+  bool stencil = false;
+  int TY3[2]{};  // rows per block of the 3-field x transforms
+  SGeo sg{};
+  int nbs = 0;   // stencil blocks (partial sums of <sigma>)
   void init(int n1, int n2, int n3);            // throws HzError for unsupported sizes
-  int nbx_max() const { return nbx[0] > nbx[1] ? nbx[0] : nbx[1]; }
+  int nbx_max() const {
+    int m = nbx[0] > nbx[1] ? nbx[0] : nbx[1];
+    return m > nbs ? m : nbs;
+  }
   int nbq_max() const { return nbq[0] > nbq[1] ? nbq[0] : nbq[1]; }
   bool same(const Shape& o) const { return geo.N1 == o.geo.N1 && geo.N2 == o.geo.N2 && geo.N3 == o.geo.N3; }
 };
@@ -115,7 +131,10 @@ size_t prob_bytes(const Shape& s, int prec, bool trace);
 ProbBuffers carve_prob(const Shape& s, int prec, bool trace, char* dev);
 
 // ---- per-kernel timing with HIP events
-enum Kind { K_ZEXP, K_YINV, K_XPASS, K_YFWD, K_ZCON, K_FINAL, K_ACCUM, K_ZERO, K_COUNT };
+enum Kind {
+  K_ZEXP, K_YINV, K_XPASS, K_YFWD, K_ZCON, K_FINAL, K_ACCUM, K_ZERO,
+  K_ZEXP3, K_YINV3, K_XC2R, K_STEN, K_XR2C, K_YFWD3, K_ZCON3, K_COUNT
+};
 extern const char* const kKindNames[K_COUNT];
 
 struct Prof {
@@ -139,6 +158,7 @@ struct Prob {
   const Shape* shape = nullptr;
   ShapeTables tab{};
   int prec = HZ_FP64;
+  int form = HZ_SCHEME_SPECTRAL;  // realisation of the iteration (same iterates either way)
   double E[6]{};
   double tol = 1e-8;
   int max_iters = 2000, fixed_iters = -1, inner_max = 400;

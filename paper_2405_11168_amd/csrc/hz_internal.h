@@ -91,7 +91,22 @@ struct ZGeo {
 // y pass geometry: contiguous rows of length N2, TX rows per tile
 struct YGeo {
   int N2, TX;
-  long long nlines;                 // 12 * H1 * N3
+  long long nlines;                 // fields * H1 * N3
+  long long off;                    // first line's element offset in the spectra (complex elements)
+};
+
+// Stencil form (same iterates as the Fourier form, eqs. DA1-DA2 in real space):
+// spectra slots of one load, in complex elements of the 12-field buffer:
+//   0..2  u: inverse z then inverse y, half spectrum along x       [3][h1][l3][l2]
+//   3..5  u on the corner grid, real                                [3][l3][l2][l1]
+//   6..8  corner force g = sum_T sigma^T(c - o) . w(o), real        [3][l3][l2][l1]
+//   9..11 g: forward x (1/N) then forward y                         [3][h1][l3][h2]
+// Real fields of N values start at element offset slot*S + c*N/2.
+constexpr int kStX = 64, kStY = 4;  // stencil tile: corners along x and y per block
+struct SGeo {
+  int N1, N2, N3;
+  int TZ;                 // corner planes per block (z segment)
+  int tx, ty, tz;         // tiles along x, y, z
 };
 
 // fused x pass geometry

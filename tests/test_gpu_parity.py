@@ -54,10 +54,15 @@ def random_problem(shape, n_phases, seed, kind="aniso", voids=False):
     return ph, C, C0, E
 
 
-def run_pair(shape, ph, C, C0, E, K, fields=True):
+SCHEMES = [hz.HZ_SCHEME_SPECTRAL, hz.HZ_SCHEME_STENCIL]
+
+
+def run_pair(shape, ph, C, C0, E, K, fields=True, scheme=hz.HZ_SCHEME_SPECTRAL):
     g = hz.Grid(*shape)
     g.set_material(C, ph)
-    r = g.solve(E, precision=hz.HZ_FP64, C0=C0, fixed_iters=K, trace=True, fields=fields)
+    if not g.scheme_available(scheme):
+        pytest.skip(f"scheme {scheme} not available for {shape}")
+    r = g.solve(E, precision=hz.HZ_FP64, C0=C0, fixed_iters=K, trace=True, fields=fields, scheme=scheme)
     ref = tetra.basic_scheme(ph, C, C0, E[0], fixed_iters=K, keep_fields=fields)
     return g, r, ref
 
@@ -96,21 +101,23 @@ def check_pair(shape, g, r, ref, K, fields=True):
     ((16, 8, 256), 2, 11, "iso", False, 2),      # radix 16 x 16 along z
     ((96, 48, 40), 2, 12, "aniso", True, 3),     # radix 3 and 5 at medium size, voids
 ])
-def test_fp64_iterates_match_oracle(shape, n_phases, seed, kind, voids, K):
-    _say(f"case shape={shape} seed={seed} kind={kind} voids={voids}")
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_fp64_iterates_match_oracle(shape, n_phases, seed, kind, voids, K, scheme):
+    _say(f"case shape={shape} seed={seed} kind={kind} voids={voids} scheme={scheme}")
     ph, C, C0, E = random_problem(shape, n_phases, seed, kind, voids)
-    g, r, ref = run_pair(shape, ph, C, C0, E, K)
+    g, r, ref = run_pair(shape, ph, C, C0, E, K, scheme=scheme)
     check_pair(shape, g, r, ref, K)
 
 
-def test_fully_anisotropic_reference_medium():
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_fully_anisotropic_reference_medium(scheme):
     """Generic (non-isotropic) reference medium: the Green operator path that contracts
     the full lambda0 tensor (eq. Green_tensor) rather than the isotropic closed form."""
     shape = (12, 10, 16)
     ph, C, _, E = random_problem(shape, 3, 21, "aniso")
     rng = np.random.default_rng(22)
     C0 = syn.random_spd_voigt(rng, 6.0, 14.0)
-    g, r, ref = run_pair(shape, ph, C, C0, E, 4)
+    g, r, ref = run_pair(shape, ph, C, C0, E, 4, scheme=scheme)
     check_pair(shape, g, r, ref, 4)
 
 
@@ -147,14 +154,15 @@ def test_batched_loads_equal_single_loads_bitwise():
         assert np.array_equal(rs.mean_sigma[0], rb.mean_sigma[J])
 
 
-def test_full_size_boolean128_first_iterates():
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_full_size_boolean128_first_iterates(scheme):
     """The 128^3 Boolean-sphere workload (contrast 1e3, 6 loads) in the launch
     configuration the benchmark times: iterates 0..2 of two loads vs the oracle."""
     p = syn.boolean128()
     g = hz.Grid(*p.shape)
     g.set_material(p.C, p.phase)
     K = 2
-    r = g.solve(p.loads, precision=hz.HZ_FP64, C0=p.C0, fixed_iters=K, trace=True)
+    r = g.solve(p.loads, precision=hz.HZ_FP64, C0=p.C0, fixed_iters=K, trace=True, scheme=scheme)
     for J in (0, 5):
         ref = tetra.basic_scheme(p.phase, p.C, p.C0, p.loads[J], fixed_iters=K, keep_fields=False)
         eh = np.max(np.abs(r.trace_residual[J, : K + 1] - ref.history) / ref.history)
@@ -163,11 +171,12 @@ def test_full_size_boolean128_first_iterates():
         assert eh < 1e-10 and em < 1e-12
 
 
-def test_fp32_refine_ceff_within_1e6_of_converged_oracle():
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_fp32_refine_ceff_within_1e6_of_converged_oracle(scheme):
     p = syn.sphere16()
     g = hz.Grid(*p.shape)
     g.set_material(p.C, p.phase)
-    Ce, r = g.effective_stiffness(tol=1e-8, C0=p.C0, precision=hz.HZ_FP32_REFINE)
+    Ce, r = g.effective_stiffness(tol=1e-8, C0=p.C0, precision=hz.HZ_FP32_REFINE, scheme=scheme)
     _say(f"  refine: status {r.status} inner iters {r.iters} rounds {r.outer_rounds} res {r.residual}")
     assert np.all(r.status == hz.HZ_OK)
     assert np.all(r.residual < 1e-8)

@@ -34,13 +34,15 @@ def _loads(n, seed):
     return rng.normal(size=(n, 6)) * 1e-3
 
 
-# (grid key, shape, seed, aniso, n_loads, precision, tol)
+# (grid key, shape, seed, aniso, n_loads, precision, tol, scheme)
+AUTO, SPEC = hz.HZ_SCHEME_AUTO, hz.HZ_SCHEME_SPECTRAL
 CASES = [
-    ("a", (16, 16, 16), 1, False, 6, hz.HZ_FP64, 1e-8),
-    ("b", (12, 10, 8), 2, True, 2, hz.HZ_FP32_REFINE, 1e-8),
-    ("c", (16, 16, 16), 3, True, 3, hz.HZ_FP64, 1e-6),       # same shape as a, other material
-    ("d", (20, 12, 14), 4, False, 1, hz.HZ_FP32_REFINE, 1e-7),
-    ("a", (16, 16, 16), 1, False, 2, hz.HZ_FP32_REFINE, 1e-9),  # same material as the first
+    ("a", (16, 16, 16), 1, False, 6, hz.HZ_FP64, 1e-8, AUTO),
+    ("b", (12, 10, 8), 2, True, 2, hz.HZ_FP32_REFINE, 1e-8, AUTO),
+    ("c", (16, 16, 16), 3, True, 3, hz.HZ_FP64, 1e-6, AUTO),       # same shape as a, other material
+    ("d", (20, 12, 14), 4, False, 1, hz.HZ_FP32_REFINE, 1e-7, AUTO),
+    ("a", (16, 16, 16), 1, False, 2, hz.HZ_FP32_REFINE, 1e-9, AUTO),  # same material as the first
+    ("c", (16, 16, 16), 3, True, 2, hz.HZ_FP64, 1e-7, SPEC),       # the Fourier form beside the stencil form
 ]
 
 
@@ -54,17 +56,17 @@ def _make():
 
 def _arena(grids, factor=1.2):
     total = 0
-    for i, (key, _s, _seed, _a, nl, prec, _t) in enumerate(CASES):
+    for i, (key, _s, _seed, _a, nl, prec, _t, _sc) in enumerate(CASES):
         total += hz.request_bytes(grids[key], prec, nl)
     return int(total * factor)
 
 
 def _alone(grids):
     out = []
-    for i, (key, _s, _seed, _a, nl, prec, tol) in enumerate(CASES):
+    for i, (key, _s, _seed, _a, nl, prec, tol, sc) in enumerate(CASES):
         g = grids[key]
         srv = hz.Server(hz.request_bytes(g, prec, nl), max_problems=8)
-        rid = srv.submit(g, _loads(nl, 100 + i), tol=tol, precision=prec)
+        rid = srv.submit(g, _loads(nl, 100 + i), tol=tol, precision=prec, scheme=sc)
         srv.drain()
         r = srv.result(rid)
         assert r is not None and r.rc >= 0, r
@@ -81,17 +83,23 @@ def test_mix_equals_alone_bitwise():
     grids = _make()
     alone = _alone(grids)
     srv = hz.Server(_arena(grids), max_problems=32, check_every=4)
-    ids = [srv.submit(grids[key], _loads(nl, 100 + i), tol=tol, precision=prec)
-           for i, (key, _s, _seed, _a, nl, prec, tol) in enumerate(CASES)]
+    ids = [srv.submit(grids[key], _loads(nl, 100 + i), tol=tol, precision=prec, scheme=sc)
+           for i, (key, _s, _seed, _a, nl, prec, tol, sc) in enumerate(CASES)]
     srv.drain()
     for i, rid in enumerate(ids):
         r = srv.result(rid)
         _say(f"  case {i}: iters {r.iters} rounds {r.outer_rounds} res {r.residual}")
         assert _same(r, alone[i]), i
     # the same loads through hz_solve (same executor, one group) agree bitwise too
-    for i, (key, _s, _seed, _a, nl, prec, tol) in enumerate(CASES):
-        rs = grids[key].solve(_loads(nl, 100 + i), tol=tol, precision=prec)
+    for i, (key, _s, _seed, _a, nl, prec, tol, sc) in enumerate(CASES):
+        rs = grids[key].solve(_loads(nl, 100 + i), tol=tol, precision=prec, scheme=sc)
         assert _same(rs, alone[i]), i
+    # the two forms iterate the same scheme: same stop iterate, <sigma> equal to rounding
+    E = _loads(2, 7)
+    r_st = grids["c"].solve(E, tol=1e-9, scheme=hz.HZ_SCHEME_STENCIL)
+    r_sp = grids["c"].solve(E, tol=1e-9, scheme=hz.HZ_SCHEME_SPECTRAL)
+    assert np.array_equal(r_st.iters, r_sp.iters)
+    assert np.abs(r_st.mean_sigma - r_sp.mean_sigma).max() < 1e-12 * np.abs(r_sp.mean_sigma).max()
 
 
 def test_continuous_arrivals_and_admission_under_memory_pressure():
@@ -99,7 +107,7 @@ def test_continuous_arrivals_and_admission_under_memory_pressure():
     so later ones wait in the queue and are admitted as memory frees up."""
     grids = _make()
     alone = _alone(grids)
-    biggest = max(hz.request_bytes(grids[k], p, n) for k, _s, _sd, _a, n, p, _t in CASES)
+    biggest = max(hz.request_bytes(grids[k], p, n) for k, _s, _sd, _a, n, p, _t, _sc in CASES)
     srv = hz.Server(int(2.05 * biggest), max_problems=16, check_every=2)
     ids = {}
     saw_queue = False
@@ -108,8 +116,8 @@ def test_continuous_arrivals_and_admission_under_memory_pressure():
     while pending or any(srv.pending()):
         if pending and tick % 3 == 0:  # one arrival every third tick
             i = pending.pop(0)
-            key, _s, _sd, _a, nl, prec, tol = CASES[i]
-            ids[i] = srv.submit(grids[key], _loads(nl, 100 + i), tol=tol, precision=prec)
+            key, _s, _sd, _a, nl, prec, tol, sc = CASES[i]
+            ids[i] = srv.submit(grids[key], _loads(nl, 100 + i), tol=tol, precision=prec, scheme=sc)
         q, _r = srv.pending()
         saw_queue |= q > 0
         srv.step()
