@@ -44,9 +44,11 @@ def log(msg):
 
 def source_digest():
     h = hashlib.sha256()
-    for f in ("hz_kernels.hip", "hz_fft.h", "hz_internal.h", "hz_api.cpp"):
-        with open(os.path.join(ROOT, "paper_2405_11168_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2405_11168_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -184,7 +184,7 @@ void Shape::init(int n1, int n2, int n3) {
   sg.N1 = G.N1;
   sg.N2 = G.N2;
   sg.N3 = G.N3;
-  sg.TZ = std::min(16, G.N3);
+  sg.TZ = std::min(kStZ, G.N3);
   sg.tx = (G.N1 + kStX - 1) / kStX;
   sg.ty = (G.N2 + kStY - 1) / kStY;
   sg.tz = (G.N3 + sg.TZ - 1) / sg.TZ;
@@ -548,7 +548,7 @@ void pass_x(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, i
 
 // P4 (forward y), P5 (forward z + contraction + update) and the stop rule
 template <typename T>
-void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n) {
+void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int c0) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
@@ -560,7 +560,7 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
   {
     const ZGeo zg = zgeo(sh, d);
     Launch L(e, K_ZCON, d);
-    L.done(launch_zcon<T>(e.d_desc, act, n, false, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
+    L.done(launch_zcon<T>(e.d_desc, act, n, false, c0, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
                           e.stream),
            "z contract");
   }
@@ -570,16 +570,17 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
 }
 
 template <typename T>
-void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso) {
+void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso, int c0) {
   pass_front<T>(e, sh, tb, act, n);
   pass_x<T>(e, sh, tb, act, n, n_iso, 0);
-  pass_back<T>(e, sh, tb, act, n);
+  pass_back<T>(e, sh, tb, act, n, c0);
 }
 
 // the same iteration in the stencil form: 3-field transforms around the real-space
 // strain / constitutive / corner-force kernel
 template <typename T>
-void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso) {
+void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso,
+                       int c0) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
@@ -620,7 +621,7 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
   }
   {
     Launch L(e, K_ZCON3, d);
-    L.done(launch_zcon<T>(e.d_desc, act, n, true, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
+    L.done(launch_zcon<T>(e.d_desc, act, n, true, c0, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
                           e.stream),
            "z contract");
   }
@@ -838,12 +839,14 @@ std::vector<Prob*> Engine::tick() {
     const int n = (int)s.ps.size();
     for (int i = 0; i < s.K; ++i) {
       const bool st = s.proto->form == HZ_SCHEME_STENCIL;
+      int c0 = 0;
+      for (const Prob* q : s.ps) c0 |= q->base.c0_iso ? 1 : 2;
       if (s.cat == 4) {
-        if (st) iteration_stencil<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
-        else iteration<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
+        if (st) iteration_stencil<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso, c0);
+        else iteration<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso, c0);
       } else {
-        if (st) iteration_stencil<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
-        else iteration<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso);
+        if (st) iteration_stencil<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso, c0);
+        else iteration<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso, c0);
       }
       hip_check(hipEventRecord(event(nev++), stream), "hipEventRecord");
     }

@@ -25,7 +25,7 @@ template <typename T>
 hipError_t launch_xfused(const Desc*, const int*, int, bool, const XGeo&, const Plan*, const Plan*, const void*,
                          hipStream_t);
 template <typename T>
-hipError_t launch_zcon(const Desc*, const int*, int, bool, const ZGeo&, const Plan*, const void*, const void*,
+hipError_t launch_zcon(const Desc*, const int*, int, bool, int, const ZGeo&, const Plan*, const void*, const void*,
                        const void*, const void*, hipStream_t);
 template <typename T>
 hipError_t launch_zexp3(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);

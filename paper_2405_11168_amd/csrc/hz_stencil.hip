@@ -1,0 +1,383 @@
+// HIP kernels (gfx950) of the stencil form of the iteration: 3-field z and x
+// transforms around the real-space strain / constitutive / corner-force kernel.
+#include "hz_device.h"
+
+namespace hz {
+
+// ----------------------------------------------------------------------------
+// Stencil form of one iteration.  The symbols of eq. Dq are the 4-corner finite
+// differences of eqs. DA1-DA2: with the library's integer corner indexing, voxel
+// r has corners r + o, o in {0,-1}^3, each with weight w(o) = o + (1/2,1/2,1/2);
+// tetrahedron T1 takes the corners with even o1+o2+o3, T2 the odd ones, and
+//   D^Tk_i[u](r) = sum_{o in Tk} w_i(o) u(r + o),
+//   g_i(c) = sum_k sum_{o in Tk} sum_j sigma^Tk_ij(c - o) w_j(o),
+// whose transform (1/N) is the residual r(q) of the Fourier form.  So only the
+// 3 displacement and 3 force components go through the transforms.
+// ----------------------------------------------------------------------------
+
+// inverse z transform of u (3 comps): u(q) -> slot 0, layout [c][h1][l3][h2]
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_zexp3(const Desc* __restrict__ descs, const int* __restrict__ active,
+                                                    ZGeo zg, const Plan* __restrict__ plan3,
+                                                    const cpx<T>* __restrict__ tw3T) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Desc& d = descs[active[blockIdx.y]];
+  if (problem_done(d)) return;
+  const int TX = zg.TX, N2 = zg.N2, N3 = zg.N3;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int h1 = tile / zg.tiles;
+  const int h2_0 = (tile % zg.tiles) * TX;
+  const int lines = 3 * TX;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* twl = buf + lines * N3;
+  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
+  __syncthreads();
+  const long long plane = (long long)h1 * N3 * N2 + h2_0;
+  const LdsAcc<T> lds{buf, 1, lines};
+  const void* usrc = d.src == 1 ? d.u64 : d.u[cur_slot(d)];
+  const GblAcc<T> src{glb(reinterpret_cast<cpx<T>*>(const_cast<void*>(usrc))) + plane, (int)zg.S, TX, 1, N2};
+  const GblAcc<T> dst{glb(reinterpret_cast<cpx<T>*>(d.spec)) + plane, (int)zg.S, TX, 1, N2};
+  fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, src, dst);
+}
+
+// C2R along x of u (slot 0 -> slot 3 real rows).  Uses the fused pass's
+// factorisation: split + first inverse pass, middle passes, last pass to HBM.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ descs, const int* __restrict__ active,
+                                                   XGeo xg, const Plan* __restrict__ planXi,
+                                                   const cpx<T>* __restrict__ twN1) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Desc& d = descs[active[blockIdx.y]];
+  if (problem_done(d)) return;
+  const int tiles2 = xg.N2 / xg.TY;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int l3 = tile / tiles2;
+  const int l2_0 = (tile % tiles2) * xg.TY;
+  const int TY = xg.TY, M = xg.M;
+  const int row0 = l3 * xg.N2 + l2_0;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* twl = buf + 3 * TY * xg.H1p;
+  for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
+  __syncthreads();
+  HZ_GLB cpx<T>* spec = glb(reinterpret_cast<cpx<T>*>(d.spec));
+  const Plan& pi = *planXi;
+  const int np = pi.np;
+  switch (pi.radix[0]) {
+    case 16: xf_load<T, 16, 3>(xg, spec + row0, buf, twl); break;
+    case 8: xf_load<T, 8, 3>(xg, spec + row0, buf, twl); break;
+    case 4: xf_load<T, 4, 3>(xg, spec + row0, buf, twl); break;
+    default: xf_load<T, 2, 3>(xg, spec + row0, buf, twl); break;
+  }
+  __syncthreads();
+  const LdsAcc<T> lds{buf, xg.H1p, 1};
+  int Ns = pi.radix[0];
+#pragma unroll 1
+  for (int p = 1; p < np - 1; ++p) {
+    pass_any<T, emax<T>(), true>(pi.radix[p], M, Ns, 3 * TY, true, twl, 2, lds, lds, true, pi.rLR[p], pi.rNs[p], 0.f);
+    __syncthreads();
+    Ns *= pi.radix[p];
+  }
+  // real row (l3, l2) of comp c as M complex values z[n] = x[2n] + i x[2n+1]
+  const int half_n = (xg.N1 / 2) * xg.N2 * xg.N3;
+  const GblAcc<T> out{spec + 3 * xg.S + (long long)row0 * M, half_n, TY, M, 1};
+  pass_any<T, emax<T>(), true>(pi.radix[np - 1], M, Ns, 3 * TY, true, twl, 2, lds, out, false, pi.rLR[np - 1],
+                               pi.rNs[np - 1], 0.f);
+}
+
+// R2C along x of the corner force g (slot 6 real rows -> slot 9), with 1/N
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ descs, const int* __restrict__ active,
+                                                   XGeo xg, const Plan* __restrict__ planXf,
+                                                   const cpx<T>* __restrict__ twN1) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Desc& d = descs[active[blockIdx.y]];
+  if (problem_done(d)) return;
+  const int tiles2 = xg.N2 / xg.TY;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int l3 = tile / tiles2;
+  const int l2_0 = (tile % tiles2) * xg.TY;
+  const int TY = xg.TY, M = xg.M;
+  const int row0 = l3 * xg.N2 + l2_0;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* twl = buf + 3 * TY * xg.H1p;
+  for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
+  __syncthreads();
+  HZ_GLB cpx<T>* spec = glb(reinterpret_cast<cpx<T>*>(d.spec));
+  const Plan& pf = *planXf;
+  const int np = pf.np;
+  const LdsAcc<T> lds{buf, xg.H1p, 1};
+  const int half_n = (xg.N1 / 2) * xg.N2 * xg.N3;
+  const GblAcc<T> in{spec + 6 * xg.S + (long long)row0 * M, half_n, TY, M, 1};
+  pass_any<T, emax<T>(), false>(pf.radix[0], M, 1, 3 * TY, true, twl, 2, in, lds, false, pf.rLR[0], pf.rNs[0], 0.f);
+  __syncthreads();
+  int Ns = pf.radix[0];
+#pragma unroll 1
+  for (int p = 1; p < np - 1; ++p) {
+    pass_any<T, emax<T>(), false>(pf.radix[p], M, Ns, 3 * TY, true, twl, 2, lds, lds, true, pf.rLR[p], pf.rNs[p], 0.f);
+    __syncthreads();
+    Ns *= pf.radix[p];
+  }
+  switch (pf.radix[np - 1]) {
+    case 16: xf_store<T, 16, 3>(xg, spec + 9 * xg.S + row0, buf, twl); break;
+    case 8: xf_store<T, 8, 3>(xg, spec + 9 * xg.S + row0, buf, twl); break;
+    case 4: xf_store<T, 4, 3>(xg, spec + 9 * xg.S + row0, buf, twl); break;
+    default: xf_store<T, 2, 3>(xg, spec + 9 * xg.S + row0, buf, twl); break;
+  }
+}
+
+// corner o in {0,-1}^3 coded as bits (bit a set: o_a = 0, clear: o_a = -1);
+// T1 takes the corners with an even number of -1 offsets
+__device__ __forceinline__ int tet_of(int o) { return ((o & 1) + ((o >> 1) & 1) + ((o >> 2) & 1)) & 1 ? 0 : 1; }
+
+// sigma^T1 (s[0..5]) and sigma^T2 (s[6..11]) of one voxel from its 8 corners u8[o][j]
+template <typename T, bool ISO>
+__device__ __forceinline__ void stencil_sigma(const Desc& d, const HZ_GLB T* C, int ph, cpx<T> lm,
+                                              const T (&u8)[8][3], T (&s)[12]) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    T G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      if (tet_of(o) != k) continue;
+      // w_i(o) = +1/2 if o_i = 0 (bit set), -1/2 if o_i = -1 (bit clear)
+      const T w0 = (o & 1) ? (T)0.5 : (T)-0.5, w1 = (o & 2) ? (T)0.5 : (T)-0.5, w2 = (o & 4) ? (T)0.5 : (T)-0.5;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        G[0][j] += w0 * u8[o][j];
+        G[1][j] += w1 * u8[o][j];
+        G[2][j] += w2 * u8[o][j];
+      }
+    }
+    T e[6];
+    e[0] = G[0][0];
+    e[1] = G[1][1];
+    e[2] = G[2][2];
+    e[3] = (T)0.5 * (G[1][2] + G[2][1]);
+    e[4] = (T)0.5 * (G[0][2] + G[2][0]);
+    e[5] = (T)0.5 * (G[0][1] + G[1][0]);
+    T out[6];
+    if (ISO) {
+      constitutive_iso<T>(lm.x, lm.y, d.Ebar, e, out);
+    } else {
+      constitutive<T>(C + ph * 24, d.Ebar, e, out);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s[6 * k + c] = out[c];
+  }
+}
+
+// Strain, constitutive law and corner force in real space.  A block owns a
+// kStX x kStY column of corners over TZ planes and streams along z: at voxel
+// plane p the corner planes p-1 and p sit in LDS (ring of two), it computes sigma
+// of the voxel plane (one halo voxel on the + side in x and y), completes the
+// force of corner plane p-1 and starts that of corner plane p.  Corner plane p+1
+// is fetched into registers one step ahead, so its latency overlaps the work.
+template <typename T, bool ISO>
+__global__ __launch_bounds__(kThreads) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
+                                                      SGeo sg) {
+  constexpr int UX = kStX + 2, UY = kStY + 2, VX = kStX + 1, VY = kStY + 1;
+  constexpr int UP = 3 * UY * UX;                      // corner values per plane
+  constexpr int NL = (UP + kThreads - 1) / kThreads;   // per thread
+  __shared__ T ub[2][UP];                              // [slot][c][yy][xx]
+  __shared__ T sb[12][VY][VX];
+  __shared__ double red[6 * 4];
+  const Desc& d = descs[active[blockIdx.y]];
+  if (problem_done(d) || (d.iso != 0) != ISO) return;
+  const int N1 = sg.N1, N2 = sg.N2, N3 = sg.N3;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int bx = tile % sg.tx, byz = tile / sg.tx;
+  const int by = byz % sg.ty, bz = byz / sg.ty;
+  const int x0 = bx * kStX, y0 = by * kStY, z0 = bz * sg.TZ;
+  const int wx = min(kStX, N1 - x0), wy = min(kStY, N2 - y0), wz = min(sg.TZ, N3 - z0);
+  const int Nn = N1 * N2 * N3, NP = N1 * N2;
+  const long long S = (long long)(N1 / 2 + 1) * N2 * N3;
+  const HZ_GLB T* ur = reinterpret_cast<const HZ_GLB T*>(glb(reinterpret_cast<const cpx<T>*>(d.spec)) + 3 * S);
+  HZ_GLB T* gr = reinterpret_cast<HZ_GLB T*>(glb(reinterpret_cast<cpx<T>*>(d.spec)) + 6 * S);
+  const HZ_GLB T* C = glb(sizeof(T) == 8 ? reinterpret_cast<const T*>(d.C64) : reinterpret_cast<const T*>(d.C32));
+  const HZ_GLB uint16_t* ph = glb(d.phase);
+  const int tid = threadIdx.x;
+  const int cx = tid % kStX, cy = tid / kStX;  // the corner this thread owns
+  const bool own = cx < wx && cy < wy;
+  // in-plane offsets of this thread's corner loads (periodic wrap)
+  int loff[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int i = tid + k * kThreads;
+    loff[k] = -1;
+    if (i < UP) {
+      const int c = i / (UY * UX), rem = i - c * (UY * UX);
+      const int yy = rem / UX, xx = rem - yy * UX;
+      int gx = x0 - 1 + xx, gy = y0 - 1 + yy;
+      while (gx < 0) gx += N1;
+      while (gx >= N1) gx -= N1;
+      while (gy < 0) gy += N2;
+      while (gy >= N2) gy -= N2;
+      loff[k] = c * Nn + gy * N1 + gx;
+    }
+  }
+  // in-plane phase-map offsets of this thread's voxels
+  const int nv = (wx + 1) * (wy + 1);
+  int voff[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int v = tid + k * kThreads;
+    const int vy = v / (wx + 1), vx = v - vy * (wx + 1);
+    int gx = x0 + vx, gy = y0 + vy;
+    while (gx >= N1) gx -= N1;
+    while (gy >= N2) gy -= N2;
+    voff[k] = gy * N1 + gx;
+  }
+  // the fetch of a plane brings its corners and the phase ids of its voxels; the
+  // stiffness entries of the isotropic case follow one step later, so no load sits
+  // on a step's critical path
+  T rg[NL];
+  int rph[2] = {0, 0}, cph[2] = {0, 0};
+  cpx<T> clm[2] = {{0, 0}, {0, 0}};
+  auto fetch = [&](int q) {
+    const int qq = q < 0 ? q + N3 : (q >= N3 ? q - N3 : q);
+    const HZ_GLB T* base = ur + (long long)qq * NP;
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if (loff[k] >= 0) rg[k] = base[loff[k]];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (tid + k * kThreads < nv) rph[k] = ph[(long long)qq * NP + voff[k]];
+  };
+  auto stash = [&](int slot) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if (loff[k] >= 0) ub[slot][tid + k * kThreads] = rg[k];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      cph[k] = rph[k];
+      if (ISO && tid + k * kThreads < nv) clm[k] = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + cph[k]);
+    }
+  };
+  fetch(z0 - 1);
+  stash((z0 + 1) & 1);
+  fetch(z0);
+  stash(z0 & 1);
+  fetch(z0 + 1);
+  T acc[3] = {0, 0, 0};
+  double sacc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+  for (int p = z0; p <= z0 + wz; ++p) {
+    const int cur = p & 1, prv = cur ^ 1;
+    __syncthreads();
+    // sigma of voxel plane p over (wx+1) x (wy+1) voxels
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int v = tid + k * kThreads;
+      if (v >= nv) continue;
+      const int vy = v / (wx + 1), vx = v - vy * (wx + 1);
+      T u8[8][3];
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        // bit a set: o_a = 0, clear: o_a = -1; corner (vx + o1, vy + o2) sits at (vx + o1 + 1, vy + o2 + 1)
+        const int ix = vx + ((o & 1) ? 1 : 0), iy = vy + ((o & 2) ? 1 : 0);
+        const int sl = (o & 4) ? cur : prv;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) u8[o][j] = ub[sl][(j * UY + iy) * UX + ix];
+      }
+      T s12[12];
+      stencil_sigma<T, ISO>(d, C, cph[k], clm[k], u8, s12);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sb[c][vy][vx] = s12[c];
+      if (vx < wx && vy < wy && p < z0 + wz) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sacc[c] += 0.5 * ((double)s12[c] + (double)s12[6 + c]);
+      }
+    }
+    __syncthreads();
+    if (own) {
+      // corner (cx, cy) receives sigma of voxel (cx - o1, cy - o2): offset -1 -> voxel +1
+      T g1[3] = {0, 0, 0}, g0[3] = {0, 0, 0};
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const int k = tet_of(o);
+        const int vx = cx + ((o & 1) ? 0 : 1), vy = cy + ((o & 2) ? 0 : 1);
+        const T w0 = (o & 1) ? (T)0.5 : (T)-0.5, w1 = (o & 2) ? (T)0.5 : (T)-0.5, w2 = (o & 4) ? (T)0.5 : (T)-0.5;
+        const T s0 = sb[6 * k + 0][vy][vx], s1 = sb[6 * k + 1][vy][vx], s2 = sb[6 * k + 2][vy][vx];
+        const T s3 = sb[6 * k + 3][vy][vx], s4 = sb[6 * k + 4][vy][vx], s5 = sb[6 * k + 5][vy][vx];
+        const T f0 = s0 * w0 + s5 * w1 + s4 * w2;
+        const T f1 = s5 * w0 + s1 * w1 + s3 * w2;
+        const T f2 = s4 * w0 + s3 * w1 + s2 * w2;
+        // o3 = 0 (bit 2 set): voxel plane = corner plane p; o3 = -1: corner plane p - 1
+        if (o & 4) {
+          g0[0] += f0; g0[1] += f1; g0[2] += f2;
+        } else {
+          g1[0] += f0; g1[1] += f1; g1[2] += f2;
+        }
+      }
+      if (p > z0) {
+        const int at = (p - 1) * NP + (y0 + cy) * N1 + (x0 + cx);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[(long long)j * Nn + at] = acc[j] + g1[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc[j] = g0[j];
+    }
+    // corner plane p+1 goes where plane p-1 was (no longer read), then fetch p+2
+    if (p < z0 + wz) {
+      stash(prv);
+      if (p + 1 < z0 + wz) fetch(p + 2);
+    }
+  }
+  block_sum<6>(sacc, red);
+  if (tid == 0) {
+    double* pp = d.part_sig + (long long)tile * 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) pp[c] = sacc[c];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// launch wrappers
+// ----------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_zexp3(const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
+                        const void* tw3T, hipStream_t s) {
+  const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
+  dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
+  hipLaunchKernelGGL(k_zexp3<T>, grid, dim3(kThreads), shm, s, descs, active, zg, plan3, (const cpx<T>*)tw3T);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xc2r(const Desc* descs, const int* active, int nact, const XGeo& xg, const Plan* planXi,
+                       const void* twN1, hipStream_t s) {
+  const size_t shm = ((size_t)3 * xg.TY * xg.H1p + xg.N1) * sizeof(cpx<T>);
+  dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY)), nact);
+  hipLaunchKernelGGL(k_xc2r<T>, grid, dim3(kThreads), shm, s, descs, active, xg, planXi, (const cpx<T>*)twN1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xr2c(const Desc* descs, const int* active, int nact, const XGeo& xg, const Plan* planXf,
+                       const void* twN1, hipStream_t s) {
+  const size_t shm = ((size_t)3 * xg.TY * xg.H1p + xg.N1) * sizeof(cpx<T>);
+  dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY)), nact);
+  hipLaunchKernelGGL(k_xr2c<T>, grid, dim3(kThreads), shm, s, descs, active, xg, planXf, (const cpx<T>*)twN1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stencil(const Desc* descs, const int* active, int nact, bool iso, const SGeo& sg, hipStream_t s) {
+  dim3 grid((unsigned)(sg.tx * sg.ty * sg.tz), nact);
+  if (iso)
+    hipLaunchKernelGGL((k_stencil<T, true>), grid, dim3(kThreads), 0, s, descs, active, sg);
+  else
+    hipLaunchKernelGGL((k_stencil<T, false>), grid, dim3(kThreads), 0, s, descs, active, sg);
+  return hipGetLastError();
+}
+
+template hipError_t launch_zexp3<double>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_zexp3<float>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xc2r<double>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xc2r<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xr2c<double>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xr2c<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_stencil<double>(const Desc*, const int*, int, bool, const SGeo&, hipStream_t);
+template hipError_t launch_stencil<float>(const Desc*, const int*, int, bool, const SGeo&, hipStream_t);
+
+}  // namespace hz
