@@ -86,7 +86,7 @@ def iteration_bytes(scheme, S, N, csz):
     return sum(kernel_bytes(k, S, N, 1, csz) for k in kinds)
 
 
-def cpu_baseline(problem, max_seconds=25.0):
+def cpu_baseline(problem, max_seconds=15.0):
     """The oracle (FP64 numpy/scipy, Algorithm 1) on a bounded sample: one load,
     a few iterations of the same 128^3 workload, timed on the host."""
     from oracle import tetra
@@ -97,7 +97,7 @@ def cpu_baseline(problem, max_seconds=25.0):
     tetra.basic_scheme(problem.phase, problem.C, problem.C0, problem.loads[0], fixed_iters=iters - 1,
                        keep_fields=False)
     dt = time.perf_counter() - t0
-    k = max(1, min(4, int(max_seconds / max(dt, 1e-3))))
+    k = max(1, min(16, int(max_seconds / max(dt, 1e-3))))
     if k > 1:
         t0 = time.perf_counter()
         tetra.basic_scheme(problem.phase, problem.C, problem.C0, problem.loads[0], fixed_iters=k - 1,
