@@ -42,9 +42,13 @@ def gradient_matrix(shape, tet):
     return B.reshape(9 * n, 3 * n)
 
 
-def minimise(phase, C, E, eps0=None):
+def minimise(phase, C, E, eps0=None, stress=False):
     """Equilibrium by direct minimisation of E(U).  Returns dict with mean stress
-    (tensor comps), the T1/T2 strain and stress fields, and the null-space dimension."""
+    (tensor comps), the T1/T2 strain and stress fields, and the null-space dimension.
+
+    stress=True: E is an applied stress sigma^a and the mean strain Ebar joins the
+    unknowns; the functional gains the external work -N sigma^a:Ebar
+    (eq. Grand_Elast_energy, d = 1), whose stationarity in Ebar is <sigma> = sigma^a."""
     phase = np.asarray(phase)
     N3, N2, N1 = phase.shape
     shape = (N1, N2, N3)
@@ -60,19 +64,39 @@ def minimise(phase, C, E, eps0=None):
                 for l in range(3):
                     L[i, j, idx, k, l, idx] = Cvox[:, i, j, k, l]
     L = L.reshape(9 * n, 9 * n)
-    Eb = voigt.sym_tensor(np.asarray(E, dtype=np.float64))
-    e_bar = np.repeat(Eb.reshape(9, 1), n, axis=1)
+    Bs = [gradient_matrix(shape, 1), gradient_matrix(shape, 2)]
+    e0f = np.zeros(9 * n)
     if eps0 is not None:
         e0 = np.stack([voigt.sym_tensor(e) for e in eps0])[phase.ravel()]  # [n,3,3]
-        e_bar = e_bar - np.moveaxis(e0, 0, -1).reshape(9, n)
-    e_bar = e_bar.reshape(9 * n)
-    Bs = [gradient_matrix(shape, 1), gradient_matrix(shape, 2)]
+        e0f = np.moveaxis(e0, 0, -1).reshape(9 * n)
     A = sum(B.T @ L @ B for B in Bs)
-    b = -sum(B.T @ L @ e_bar for B in Bs)
-    U, *_ = np.linalg.lstsq(A, b, rcond=None)
+    if stress:
+        # P: the six independent components of Ebar -> the uniform 9N strain field
+        P = np.zeros((9, n, 6))
+        for m, (i, j) in enumerate(voigt.PAIRS):
+            P[i * 3 + j, :, m] = 1.0
+            P[j * 3 + i, :, m] = 1.0
+        P = P.reshape(9 * n, 6)
+        Sa = voigt.sym_tensor(np.asarray(E, dtype=np.float64))
+        work = P.T @ np.repeat(Sa.reshape(9, 1), n, axis=1).reshape(9 * n)  # d(sigma^a:Ebar)/de_m per voxel, summed
+        # dE/dU = 1/2 sum_k B_k^T L (P e + B_k U - e0) = 0
+        # dE/de = 1/2 sum_k P^T L (P e + B_k U - e0) - N sigma^a:dEbar/de = 0
+        BLP = sum(B.T @ L @ P for B in Bs)
+        K = np.block([[A, BLP], [BLP.T, 2.0 * P.T @ L @ P]])
+        rhs = np.concatenate([sum(B.T @ L @ e0f for B in Bs),
+                              2.0 * P.T @ L @ e0f + 2.0 * work])
+        x, *_ = np.linalg.lstsq(K, rhs, rcond=None)
+        U, e = x[:3 * n], x[3 * n:]
+        Eb = (P.reshape(9, n, 6)[:, 0, :] @ e).reshape(3, 3)
+    else:
+        Eb = voigt.sym_tensor(np.asarray(E, dtype=np.float64))
+        b = -sum(B.T @ L @ (np.repeat(Eb.reshape(9, 1), n, axis=1).reshape(9 * n) - e0f)
+                 for B in Bs)
+        U, *_ = np.linalg.lstsq(A, b, rcond=None)
+    e_bar = np.repeat(Eb.reshape(9, 1), n, axis=1).reshape(9 * n) - e0f
     w = np.linalg.eigvalsh(A)
     null_dim = int(np.sum(np.abs(w) <= 1e-10 * np.max(np.abs(w))))
-    out = {"U": U, "null_dim": null_dim}
+    out = {"U": U, "null_dim": null_dim, "Ebar": voigt.sym_vector(Eb)}
     sig = []
     for k, B in enumerate(Bs, start=1):
         eps = (Eb.reshape(9, 1) + (B @ U).reshape(9, n)).reshape(3, 3, N3, N2, N1)

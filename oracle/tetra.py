@@ -153,25 +153,42 @@ class Result(dict):
 
 
 def basic_scheme(phase, C, C0, E, tol=1e-8, max_iters=1000, eps0=None, fixed_iters=None,
-                 keep_fields=True, keep_spectra=False):
+                 keep_fields=True, keep_spectra=False, stress=False):
     """Displacement-based basic scheme for the tetrahedral stencil (Algorithm 1).
 
     phase : [N3, N2, N1] integer phase map; C : [P, 6, 6] Voigt stiffness per phase;
     C0 : [6, 6] reference medium; E : applied mean strain, tensor comps (11,22,33,23,13,12);
     eps0 : optional [P, 6] eigenstrain per phase (tensor comps).
+    stress=True: E is the applied stress sigma^a instead (Sec. 2.5); the mean strain
+    starts at lambda0^-1:sigma^a and follows step 6 of Algorithm 1 after every update.
 
     Iterate k = 0, 1, ...: build the fields of u_k, measure eps_k = L2/||<sigma>||
     (eqs. L2-norm, tolerance), stop at the first k with eps_k < tol (or at k =
     fixed_iters when given), otherwise apply the update of eq. basic_scheme_dep_2.
-    The reported iterate is u_k, i.e. `iters` updates were applied."""
+    The reported iterate is u_k, i.e. `iters` updates were applied.  Under applied
+    stress eps_k = L2/s with the fixed scale s = ||sigma^a|| (||<lambda:eps0>|| when
+    sigma^a = 0), and the stop also needs ||<sigma>_k - sigma^a|| <= tol s (the loop
+    on the mean strain has converged too)."""
     phase = np.asarray(phase)
     N3, N2, N1 = phase.shape
     shape = (N1, N2, N3)
     Ct = np.stack([voigt.stiffness_tensor(c) for c in C])
     C0t = voigt.stiffness_tensor(C0)
-    Eb = voigt.sym_tensor(np.asarray(E, dtype=np.float64))
     e0t = None if eps0 is None else np.stack([voigt.sym_tensor(e) for e in eps0])
     pidx = _phase_indices(phase, len(C))
+    if stress:
+        Sa = voigt.sym_tensor(np.asarray(E, dtype=np.float64))
+        Eb = voigt.solve_stiffness(C0, Sa)  # initial guess lambda0^-1 : sigma^a
+        frac = np.array([idx.size for idx in pidx], dtype=np.float64) / phase.size
+        C_mean = np.einsum("p,pijkl->ijkl", frac, Ct)  # <lambda>
+        Ce0_mean = (np.zeros((3, 3)) if e0t is None
+                    else np.einsum("p,pijkl,pkl->ij", frac, Ct, e0t))  # <lambda:eps0>
+        # stress scale of the stop rule: the target ||sigma^a||, or the eigenstress
+        # ||<lambda:eps0>|| when no stress is applied (<sigma> then tends to zero)
+        s_ref = voigt.frobenius(Sa) or voigt.frobenius(Ce0_mean) or 1.0
+    else:
+        Eb = voigt.sym_tensor(np.asarray(E, dtype=np.float64))
+    Eb_hist = []
 
     D = D_symbol(shape)
     Om = green(D, C0t, shape)
@@ -200,20 +217,31 @@ def basic_scheme(phase, C, C0, E, tol=1e-8, max_iters=1000, eps0=None, fixed_ite
         r = dot_vec(s1q, np.conj(D)) - dot_vec(s2q, D)
         L2 = float(np.sqrt(np.sum(np.abs(r / 2) ** 2)))
         mean_sigma = 0.5 * (s1.mean(axis=(-3, -2, -1)) + s2.mean(axis=(-3, -2, -1)))
-        nrm = voigt.frobenius(mean_sigma)
+        nrm = s_ref if stress else voigt.frobenius(mean_sigma)
         err = L2 / nrm if nrm > 0 else L2
         hist.append(err)
         means.append(voigt.sym_vector(mean_sigma))
-        done = (err < tol) if fixed_iters is None else (k >= fixed_iters)
+        Eb_hist.append(voigt.sym_vector(Eb))
+        conv = err < tol
+        if stress:
+            conv = conv and voigt.frobenius(mean_sigma - Sa) <= tol * s_ref
+        done = conv if fixed_iters is None else k >= fixed_iters
         if done or k >= max_iters:
             break
         # step 5: u <- u - Omega.r
         u = u - np.einsum("il...,l...->i...", Om, r)
+        if stress:
+            # step 6: Ebar <- lambda0^-1 : {sigma^a + (lambda0 - <lambda>):Ebar - <lambda:deps> + <lambda:eps0>}
+            deps = 0.5 * (de1 + de2)
+            C_deps = constitutive(deps, pidx, Ct).mean(axis=(-3, -2, -1))
+            rhs = Sa + np.einsum("ijkl,kl->ij", C0t - C_mean, Eb) - C_deps + Ce0_mean
+            Eb = voigt.solve_stiffness(C0, rhs)
         k += 1
 
-    out = Result(iters=k, converged=bool(err < tol), residual=err, history=np.array(hist),
+    out = Result(iters=k, converged=bool(conv), residual=err, history=np.array(hist),
                  mean_sigma=voigt.sym_vector(mean_sigma), mean_history=np.array(means),
-                 L2=L2, max_imag=float(imag), u_hat=u)
+                 L2=L2, max_imag=float(imag), u_hat=u, Ebar=voigt.sym_vector(Eb),
+                 Ebar_history=np.array(Eb_hist))
     if keep_fields:
         # final fields are the T1/T2 averages (eq. final_fields)
         out["eps"] = voigt.sym_vector(0.5 * (eps1 + eps2))

@@ -39,3 +39,13 @@ def sym_vector(t):
 def frobenius(t):
     """Frobenius norm over all nine components of a 3x3 tensor."""
     return float(np.sqrt(np.sum(np.abs(t) ** 2)))
+
+
+def solve_stiffness(C, Y):
+    """X with C:X = Y for a Voigt stiffness C and a symmetric 3x3 tensor Y, i.e. the
+    action of the inverse stiffness (compliance) on symmetric tensors.  Written in the
+    Mandel basis, where the double contraction is an ordinary 6x6 product."""
+    s = np.array([1, 1, 1, np.sqrt(2.0), np.sqrt(2.0), np.sqrt(2.0)])
+    M = np.asarray(C, dtype=np.float64) * np.outer(s, s)
+    y = sym_vector(np.asarray(Y, dtype=np.float64)) * s
+    return sym_tensor(np.linalg.solve(M, y) / s)
