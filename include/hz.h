@@ -8,12 +8,17 @@
  *
  *   1. eps^T1(q) = D(q) (x)_s u(q),  eps^T2(q) = -conj(D(q)) (x)_s u(q)   (eq. deps_dep_Q)
  *   2. inverse FFT of the twelve strain components                          (eq. IFT_1)
- *   3. sigma^Tk(r) = lambda(r) : (Ebar + eps^Tk(r))                          (eq. linear_elasticity_Kk)
+ *   3. sigma^Tk(r) = lambda(r) : (Ebar + eps^Tk(r) - eps0(r))                (eq. linear_elasticity_Kk)
  *   4. forward FFT                                                          (eq. FT)
  *   5. u(q) <- u(q) - Omega(q).{sigma^T1(q).conj(D(q)) - sigma^T2(q).D(q)}   (eq. basic_scheme_dep_2)
  *
  * with D of eq. Dq, Omega of eq. Green_tensor (set to 0 at q = 0 and q = (pi,pi,pi)),
  * and the convergence measure eps = L2/||<sigma>|| of eqs. L2-norm and tolerance.
+ * Under an applied stress (Sec. 2.5) the mean strain Ebar is an unknown too:
+ *
+ *   6. Ebar <- lambda0^-1 : {sigma^a + (lambda0 - <lambda>):Ebar - <lambda:deps> + <lambda:eps0>}
+ *
+ * starting from Ebar = lambda0^-1 : sigma^a.  Per-phase eigenstrains eps0 are optional.
  * Every step runs in hand-written HIP kernels on device-resident fields.
  *
  * Conventions
@@ -76,6 +81,15 @@ typedef struct hz_grid_s* hz_grid;
  *   space, so only the 3 displacement and 3 force components are transformed
  *   (needs N1/2 with a power-of-two factor, see hz_scheme_available).
  * HZ_SCHEME_AUTO: the stencil form where available, else the spectral one. */
+/* Loading (Sec. 2.3 and Sec. 2.5).  Under HZ_LOAD_STRESS the six numbers of a load
+ * are the applied stress sigma^a; the run stops at the first iterate k with
+ *   L2_k / s < tol  and  ||<sigma>_k - sigma^a|| <= tol * s
+ * where s = ||sigma^a|| (Frobenius), or ||<lambda:eps0>|| when sigma^a = 0 (then
+ * <sigma> tends to zero, and the measure of eq. tolerance is undefined), or 1 when
+ * both vanish.  HZ_LOAD_STRESS needs HZ_FP64. */
+#define HZ_LOAD_STRAIN 0
+#define HZ_LOAD_STRESS 1
+
 #define HZ_SCHEME_AUTO 0
 #define HZ_SCHEME_SPECTRAL 1
 #define HZ_SCHEME_STENCIL 2
@@ -93,6 +107,7 @@ typedef struct {
   double inner_rho;         /* refinement: inner loop stops at rho * eps of its FP64 sweep      */
   int32_t inner_max;        /* refinement: cap on inner iterations per outer round              */
   int32_t scheme;           /* HZ_SCHEME_AUTO, HZ_SCHEME_SPECTRAL or HZ_SCHEME_STENCIL           */
+  int32_t loading;          /* HZ_LOAD_STRAIN (E is the mean strain) or HZ_LOAD_STRESS            */
 } hz_opts;
 
 typedef struct {
@@ -105,11 +120,13 @@ typedef struct {
   double seconds_to_1e6;    /* device time to the first FP64-verified eps < 1e-6, or -1         */
   double wall_seconds;      /* host wall time: the hz_solve call, or a served request from
                                submission to the step that saw it finish (queueing included)     */
+  double Ebar[6];           /* mean strain of the reported iterate (tensor comps): the applied
+                               strain, or the converged loop of Sec. 2.5 under applied stress     */
 } hz_info;
 
 /* Fill *o with defaults: tol 1e-8, max_iters 2000, HZ_FP64, automatic reference,
  * fixed_iters -1, check_every 8, no traces, inner_rho 1e-3, inner_max 400,
- * HZ_SCHEME_AUTO. */
+ * HZ_SCHEME_AUTO, HZ_LOAD_STRAIN. */
 void hz_default_opts(hz_opts* o);
 
 /* Create a grid handle for an n1 x n2 x n3 periodic cell (Sec. 2.1).
@@ -119,8 +136,16 @@ int hz_create_grid(int32_t n1, int32_t n2, int32_t n3, hz_grid* out);
 /* Set the microstructure: n_phases stiffness matrices C_voigt[n_phases][6][6]
  * and the phase id of every voxel phase[n3][n2][n1] (< n_phases).  Zero
  * stiffness (voids) is allowed.  Host arrays are copied; device copies are made
- * by hz_bind_workspace. */
+ * by hz_bind_workspace.  Clears eigenstrains set before. */
 int hz_set_material(hz_grid g, int32_t n_phases, const double* C_voigt, const uint16_t* phase);
+
+/* Per-phase eigenstrains eps0[n_phases][6] (tensor comps; eq. linear_elasticity:
+ * sigma = lambda:(eps - eps0)), for the material currently set; NULL clears them.
+ * Copied; hz_set_material clears them.  Like a material change, it takes effect at
+ * the next hz_bind_workspace (requests already submitted to a server keep theirs).
+ * HZ_ENOMATERIAL before hz_set_material, HZ_EINVAL for a row count other than the
+ * material's phase count or a non-finite entry. */
+int hz_set_eigenstrain(hz_grid g, int32_t n_phases, const double* eps0);
 
 /* Bytes of device workspace needed to solve up to n_loads load cases at once
  * in the given precision; negative error code on invalid arguments. */
@@ -133,8 +158,9 @@ int64_t hz_workspace_bytes(hz_grid g, int32_t precision, int32_t n_loads);
 int hz_bind_workspace(hz_grid g, void* dev_ptr, int64_t bytes, void* hip_stream,
                       int32_t precision, int32_t n_loads);
 
-/* Solve n_loads strain-controlled problems with applied mean strains E[n_loads][6]
- * (Sec. 2.3: the mean strain equals the applied strain).
+/* Solve n_loads problems: applied mean strains E[n_loads][6] (HZ_LOAD_STRAIN, Sec. 2.3:
+ * the mean strain equals the applied strain) or applied stresses (HZ_LOAD_STRESS,
+ * Sec. 2.5), tensor comps.
  * Outputs (each may be NULL):
  *   sigma_mean[n_loads][6]  <sigma> of the reported iterate (FP64)
  *   eps_out, sig_out        host [n_loads][6][n3][n2][n1] FP64 fields of eq. final_fields
@@ -145,7 +171,8 @@ int hz_solve(hz_grid g, int32_t n_loads, const double* E, const hz_opts* o,
 
 /* Effective stiffness: the six unit load cases (gamma_J = 1) solved as one batch;
  * column J of C_eff (row-major 6x6 Voigt) is <sigma> of case J.  Needs a workspace
- * bound for n_loads >= 6. */
+ * bound for n_loads >= 6, strain loading and a material without eigenstrains
+ * (HZ_EINVAL otherwise). */
 int hz_effective_stiffness(hz_grid g, const hz_opts* o, double C_eff[36], hz_info info[6]);
 
 /* Copy the displacement spectrum of load `load` after the last solve to host:
@@ -209,10 +236,11 @@ int64_t hz_request_bytes(hz_grid g, int32_t precision, int32_t n_loads);
 int hz_server_create(void* dev_ptr, int64_t bytes, void* hip_stream, int32_t max_problems,
                      int32_t check_every, hz_server* out);
 
-/* Queue a request: the material currently set on g (shared, copy-on-write: a
- * later hz_set_material on g does not affect it), n_loads strains E[n_loads][6]
- * and options o (tol, max_iters, precision, reference medium, inner_rho,
- * inner_max; fixed_iters and traces are not served).  Writes the request id.
+/* Queue a request: the material currently set on g, with its eigenstrains (shared,
+ * copy-on-write: a later hz_set_material or hz_set_eigenstrain on g does not affect
+ * it), n_loads loads E[n_loads][6] and options o (tol, max_iters, precision,
+ * reference medium, inner_rho, inner_max, scheme, loading; fixed_iters and traces
+ * are not served).  Writes the request id.
  * HZ_EWORKSPACE if the request could never fit the workspace or slots. */
 int hz_server_submit(hz_server s, hz_grid g, int32_t n_loads, const double* E, const hz_opts* o,
                      int64_t* id);

@@ -14,10 +14,12 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (HZ_EDIVERGED, HZ_FP32_REFINE, HZ_FP64, HZ_NOT_CONVERGED, HZ_OK, HZ_PENDING, HZ_SCHEME_AUTO,
-                   HZ_SCHEME_SPECTRAL, HZ_SCHEME_STENCIL, HZ_STAGNATED, HzError, check, hz_info, hz_opts)
+from ._abi import (HZ_EDIVERGED, HZ_FP32_REFINE, HZ_FP64, HZ_LOAD_STRAIN, HZ_LOAD_STRESS, HZ_NOT_CONVERGED, HZ_OK,
+                   HZ_PENDING, HZ_SCHEME_AUTO, HZ_SCHEME_SPECTRAL, HZ_SCHEME_STENCIL, HZ_STAGNATED, HzError, check,
+                   hz_info, hz_opts)
 
-__all__ = ["Grid", "Server", "SolveResult", "HZ_FP64", "HZ_FP32_REFINE", "HzError", "reference_medium", "lib"]
+__all__ = ["Grid", "Server", "SolveResult", "HZ_FP64", "HZ_FP32_REFINE", "HZ_LOAD_STRAIN", "HZ_LOAD_STRESS", "HzError",
+           "reference_medium", "lib"]
 
 
 def lib():
@@ -37,7 +39,7 @@ def reference_medium(C):
 
 
 def _opts(tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1, check_every=8, inner_rho=1e-3,
-          inner_max=400, scheme=HZ_SCHEME_AUTO):
+          inner_max=400, scheme=HZ_SCHEME_AUTO, loading=HZ_LOAD_STRAIN):
     o = hz_opts()
     lib().hz_default_opts(ctypes.byref(o))
     o.tol = tol
@@ -48,6 +50,7 @@ def _opts(tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1, 
     o.inner_rho = inner_rho
     o.inner_max = inner_max
     o.scheme = scheme
+    o.loading = loading
     if C0 is not None:
         o.ref_mode = 1
         o.ref_C[:] = np.asarray(C0, dtype=np.float64).reshape(36).tolist()
@@ -63,7 +66,8 @@ def _result(sm, infos, rc, **kw):
         residual=np.array([i.residual for i in infos]),
         seconds=np.array([i.seconds for i in infos]),
         seconds_to_1e6=np.array([i.seconds_to_1e6 for i in infos]),
-        rc=rc, wall_seconds=np.array([i.wall_seconds for i in infos]), **kw)
+        rc=rc, wall_seconds=np.array([i.wall_seconds for i in infos]),
+        Ebar=np.array([list(i.Ebar) for i in infos]), **kw)
 
 
 @dataclass
@@ -77,6 +81,7 @@ class SolveResult:
     seconds_to_1e6: np.ndarray
     rc: int
     wall_seconds: np.ndarray | None = None
+    Ebar: np.ndarray | None = None             # [n_loads, 6] mean strain of the reported iterate
     trace_residual: np.ndarray | None = None   # [n_loads, T]
     trace_mean: np.ndarray | None = None       # [n_loads, T, 6]
     eps: np.ndarray | None = None              # [n_loads, 6, N3, N2, N1]
@@ -116,6 +121,15 @@ class Grid:
                                     phase.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))))
         self._bound = None
 
+    def set_eigenstrain(self, eps0):
+        """eps0: [P,6] per-phase eigenstrain (tensor comps), or None to clear."""
+        if eps0 is None:
+            check(lib().hz_set_eigenstrain(self._h, 0, None))
+        else:
+            e = np.ascontiguousarray(eps0, dtype=np.float64).reshape(-1, 6)
+            check(lib().hz_set_eigenstrain(self._h, len(e), _dptr(e)))
+        self._bound = None
+
     # -- workspace -------------------------------------------------------------
     def workspace_bytes(self, precision=HZ_FP64, n_loads=1) -> int:
         return check(lib().hz_workspace_bytes(self._h, precision, n_loads))
@@ -142,11 +156,12 @@ class Grid:
     # -- solve -----------------------------------------------------------------
     def solve(self, E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1,
               fields=False, trace=False, check_every=8, inner_rho=1e-3, inner_max=400,
-              scheme=HZ_SCHEME_AUTO) -> SolveResult:
+              scheme=HZ_SCHEME_AUTO, loading=HZ_LOAD_STRAIN) -> SolveResult:
+        """E: [n_loads, 6] applied mean strains, or applied stresses with loading=HZ_LOAD_STRESS."""
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
         nl = E.shape[0]
         self._ensure(precision, nl)
-        o = _opts(tol, max_iters, precision, C0, fixed_iters, check_every, inner_rho, inner_max, scheme)
+        o = _opts(tol, max_iters, precision, C0, fixed_iters, check_every, inner_rho, inner_max, scheme, loading)
         T = (fixed_iters if fixed_iters >= 0 else max_iters) + 1
         tr = tm = None
         if trace:
@@ -230,9 +245,9 @@ class Server:
             self._h = None
 
     def submit(self, grid: "Grid", E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, inner_rho=1e-3,
-               inner_max=400, scheme=HZ_SCHEME_AUTO) -> int:
+               inner_max=400, scheme=HZ_SCHEME_AUTO, loading=HZ_LOAD_STRAIN) -> int:
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
-        o = _opts(tol, max_iters, precision, C0, -1, 8, inner_rho, inner_max, scheme)
+        o = _opts(tol, max_iters, precision, C0, -1, 8, inner_rho, inner_max, scheme, loading)
         rid = ctypes.c_int64()
         check(lib().hz_server_submit(self._h, grid._h, E.shape[0], _dptr(E), ctypes.byref(o), ctypes.byref(rid)))
         self._nloads[rid.value] = E.shape[0]

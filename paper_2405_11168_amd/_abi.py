@@ -25,6 +25,9 @@ HZ_SCHEME_AUTO = 0
 HZ_SCHEME_SPECTRAL = 1
 HZ_SCHEME_STENCIL = 2
 
+HZ_LOAD_STRAIN = 0
+HZ_LOAD_STRESS = 1
+
 
 class hz_opts(ctypes.Structure):
     _fields_ = [
@@ -40,6 +43,7 @@ class hz_opts(ctypes.Structure):
         ("inner_rho", c_double),
         ("inner_max", c_int32),
         ("scheme", c_int32),
+        ("loading", c_int32),
     ]
 
 
@@ -53,6 +57,7 @@ class hz_info(ctypes.Structure):
         ("seconds", c_double),
         ("seconds_to_1e6", c_double),
         ("wall_seconds", c_double),
+        ("Ebar", c_double * 6),
     ]
 
 
@@ -61,6 +66,7 @@ SIGNATURES = {
     "hz_default_opts": (None, [POINTER(hz_opts)]),
     "hz_create_grid": (c_int32, [c_int32, c_int32, c_int32, POINTER(c_void_p)]),
     "hz_set_material": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_uint16)]),
+    "hz_set_eigenstrain": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "hz_workspace_bytes": (c_int64, [c_void_p, c_int32, c_int32]),
     "hz_bind_workspace": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_int32]),
     "hz_solve": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(hz_opts), POINTER(c_double),

@@ -27,10 +27,6 @@ namespace {
 
 thread_local std::string g_err;
 
-size_t material_bytes(int np, long long N) {
-  return align_up((size_t)np * 24 * 8) + align_up((size_t)np * 24 * 4) + align_up((size_t)N * 2);
-}
-
 void check_opts(const hz_opts& o) {
   if (o.precision != HZ_FP64 && o.precision != HZ_FP32_REFINE) fail(HZ_EINVAL, "unknown precision");
   if (!(o.tol > 0) && o.fixed_iters < 0) fail(HZ_EINVAL, "tol must be > 0");
@@ -38,6 +34,8 @@ void check_opts(const hz_opts& o) {
   if (o.fixed_iters > kTraceCap - 1) fail(HZ_EINVAL, "fixed_iters out of range");
   if (o.inner_max < 0 || o.inner_max > 100000) fail(HZ_EINVAL, "inner_max out of range");
   if (o.scheme < HZ_SCHEME_AUTO || o.scheme > HZ_SCHEME_STENCIL) fail(HZ_EINVAL, "unknown scheme");
+  if (o.loading != HZ_LOAD_STRAIN && o.loading != HZ_LOAD_STRESS) fail(HZ_EINVAL, "unknown loading");
+  if (o.loading == HZ_LOAD_STRESS && o.precision != HZ_FP64) fail(HZ_EINVAL, "applied stress needs HZ_FP64");
 }
 
 int pick_form(const Shape& sh, int scheme) {
@@ -48,7 +46,7 @@ int pick_form(const Shape& sh, int scheme) {
 
 void check_loads(const double* E, int n) {
   for (int i = 0; i < 6 * n; ++i)
-    if (!std::isfinite(E[i])) fail(HZ_EINVAL, "non-finite applied strain");
+    if (!std::isfinite(E[i])) fail(HZ_EINVAL, "non-finite applied load");
 }
 
 // one load case ready for the executor
@@ -60,7 +58,19 @@ void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, cons
   p.tab = tab;
   p.prec = o.precision;
   p.form = pick_form(*sh, o.scheme);
+  p.loading = o.loading;
   for (int c = 0; c < 6; ++c) p.E[c] = E[c];
+  if (o.loading == HZ_LOAD_STRESS) {
+    // initial mean strain lambda0^-1:sigma^a (Algorithm 1)
+    for (int i = 0; i < 6; ++i) {
+      double a = 0;
+      for (int j = 0; j < 6; ++j) a += R.S0[i * 6 + j] * E[j];
+      p.Eb0[i] = a;
+    }
+  } else {
+    for (int c = 0; c < 6; ++c) p.Eb0[c] = E[c];
+  }
+  for (int c = 0; c < 6; ++c) p.Ebar[c] = p.Eb0[c];
   p.tol = o.tol;
   p.max_iters = o.max_iters;
   p.fixed_iters = o.precision == HZ_FP64 ? o.fixed_iters : -1;
@@ -83,6 +93,20 @@ void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, cons
   d.part_sig = b.part_sig;
   d.part_res = b.part_res;
   d.trace = b.trace;
+  d.tau64 = mt.tau64;
+  d.tau32 = mt.tau32;
+  d.loading = o.loading;
+  if (o.loading == HZ_LOAD_STRESS) {
+    auto frob = [](const double* t) {
+      return std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + 2.0 * (t[3] * t[3] + t[4] * t[4] + t[5] * t[5]));
+    };
+    for (int c = 0; c < 6; ++c) d.sig_a[c] = E[c];
+    std::memcpy(d.S0, R.S0, sizeof(d.S0));
+    // stop-rule scale: ||sigma^a||, else the eigenstress scale ||<lambda:eps0>||, else 1
+    d.sref = frob(E);
+    if (!(d.sref > 0)) d.sref = frob(m.tau_mean);
+    if (!(d.sref > 0)) d.sref = 1.0;
+  }
   std::memcpy(d.C0, R.C0t, sizeof(d.C0));
 }
 
@@ -101,6 +125,7 @@ void fill_info(const Prob& p, double t0_ms, double wall, hz_info& in) {
   in.seconds = 1e-3 * (p.t_done - t0_ms);
   in.seconds_to_1e6 = p.t_1e6 >= 0 ? 1e-3 * (p.t_1e6 - t0_ms) : -1.0;
   in.wall_seconds = wall;
+  for (int c = 0; c < 6; ++c) in.Ebar[c] = p.Ebar[c];
 }
 
 // first-fit allocator over a byte range, 256-byte granules, neighbours coalesced
@@ -181,7 +206,7 @@ void grid_layout(const hz_grid_s* g, int prec, int nl, hz_grid_s::Off& o) {
     return r;
   };
   o.shape_tab = take(shape_table_bytes(g->shape));
-  o.mat_tab = take(material_bytes(g->mat ? g->mat->n_phases : 1, g->shape.geo.N));
+  o.mat_tab = take(material_table_bytes(g->mat ? g->mat->n_phases : 1, g->shape.geo.N));
   o.engine = take(Engine::table_bytes(nl));
   o.fields = take((size_t)12 * g->shape.geo.N * 8);
   o.pb = prob_bytes(g->shape, prec, true);
@@ -417,6 +442,7 @@ void hz_default_opts(hz_opts* o) {
   o->inner_rho = 1e-3;
   o->inner_max = 400;
   o->scheme = HZ_SCHEME_AUTO;
+  o->loading = HZ_LOAD_STRAIN;
 }
 
 const char* hz_last_error(void) { return g_err.c_str(); }
@@ -441,6 +467,17 @@ int hz_set_material(hz_grid g, int32_t n_phases, const double* C_voigt, const ui
   HZ_GUARD_BEGIN
   if (!g) fail(HZ_EINVAL, "NULL handle");
   g->mat = make_material(g->shape.geo, n_phases, C_voigt, phase);
+  g->ws = nullptr;  // tables must be re-uploaded
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
+int hz_set_eigenstrain(hz_grid g, int32_t n_phases, const double* eps0) {
+  HZ_GUARD_BEGIN
+  if (!g) fail(HZ_EINVAL, "NULL handle");
+  if (!g->mat) fail(HZ_ENOMATERIAL, "material not set");
+  if (eps0 && n_phases != g->mat->n_phases) fail(HZ_EINVAL, "eigenstrain table must have one row per phase");
+  g->mat = with_eigenstrain(*g->mat, eps0);
   g->ws = nullptr;  // tables must be re-uploaded
   return HZ_OK;
   HZ_GUARD_END
@@ -494,11 +531,11 @@ int hz_solve(hz_grid g, int32_t n_loads, const double* E, const hz_opts* o, doub
              double* sig_out, hz_info* info) {
   HZ_GUARD_BEGIN
   if (!g || !E || !o || n_loads <= 0) fail(HZ_EINVAL, "bad solve arguments");
+  check_opts(*o);
+  check_loads(E, n_loads);
   check_bound(g);
   if (n_loads > g->cap) fail(HZ_EWORKSPACE, "workspace bound for fewer loads");
   if (o->precision != g->prec) fail(HZ_EWORKSPACE, "workspace bound for another precision");
-  check_opts(*o);
-  check_loads(E, n_loads);
   return grid_solve(g, n_loads, E, *o, sigma_mean, eps_out, sig_out, info);
   HZ_GUARD_END
 }
@@ -506,6 +543,8 @@ int hz_solve(hz_grid g, int32_t n_loads, const double* E, const hz_opts* o, doub
 int hz_effective_stiffness(hz_grid g, const hz_opts* o, double C_eff[36], hz_info info[6]) {
   HZ_GUARD_BEGIN
   if (!g || !o || !C_eff) fail(HZ_EINVAL, "bad arguments");
+  if (o->loading != HZ_LOAD_STRAIN) fail(HZ_EINVAL, "the effective stiffness takes unit strains");
+  if (g->mat && !g->mat->eig.empty()) fail(HZ_EINVAL, "the effective stiffness needs a material without eigenstrains");
   double E[36] = {0};
   for (int J = 0; J < 6; ++J) E[J * 6 + J] = J < 3 ? 1.0 : 0.5;
   double sm[36];

@@ -87,14 +87,59 @@ __device__ __forceinline__ void affine_symbols(cpx<double> t1, cpx<double> t2, c
   b2[0] = P; b2[1] = P; b2[2] = mS;
 }
 
-// sigma = C:(Ebar + deps) in tensor comps (11,22,33,23,13,12); C as an engineering
-// Voigt matrix stored as its upper triangle (21 of 24 slots) row by row
+// A wave-uniform value moved into scalar registers.
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// What the constitutive law of one problem needs besides the stiffness: the mean
+// strain of the current iterate (status block, in kernel precision) and the
+// per-phase eigenstress table.
 template <typename T>
-__device__ __forceinline__ void constitutive(const HZ_GLB T* __restrict__ Cp, const double* Eb, const T (&de)[6],
-                                             T (&s)[6]) {
+struct Mean {
+  T Eb[6];
+  const HZ_GLB T* tau;  // [n_phases][8] lambda_p:eps0_p, or null
+};
+template <typename T>
+__device__ __forceinline__ Mean<T> mean_state(const Desc& d) {
+  Mean<T> m;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) m.Eb[c] = uniform((T)d.status[ST_EBAR + c]);
+  const T* t;
+  if constexpr (sizeof(T) == 8) t = reinterpret_cast<const T*>(d.tau64);
+  else t = reinterpret_cast<const T*>(d.tau32);
+  m.tau = glb(t);
+  return m;
+}
+// sigma -= lambda_p:eps0_p (eq. linear_elasticity with an eigenstrain); EIG: the
+// problem has eigenstrains (its table pointer is not null)
+template <bool EIG, typename T>
+__device__ __forceinline__ void eigenstress(const Mean<T>& M, int ph, T (&s)[6]) {
+  if constexpr (EIG) {
+    const HZ_GLB cpx<T>* t = reinterpret_cast<const HZ_GLB cpx<T>*>(M.tau + ph * 8);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const cpx<T> v = gld(t + i);
+      s[2 * i] -= v.x;
+      s[2 * i + 1] -= v.y;
+    }
+  }
+}
+
+// sigma = C:(Ebar + deps) - lambda:eps0 in tensor comps (11,22,33,23,13,12); C as an
+// engineering Voigt matrix stored as its upper triangle (21 of 24 slots) row by row
+template <bool EIG, typename T>
+__device__ __forceinline__ void constitutive(const HZ_GLB T* __restrict__ Cp, const Mean<T>& M, int ph,
+                                             const T (&de)[6], T (&s)[6]) {
   T g[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) g[c] = (T)Eb[c] + de[c];
+  for (int c = 0; c < 6; ++c) g[c] = M.Eb[c] + de[c];
   g[3] *= (T)2; g[4] *= (T)2; g[5] *= (T)2;  // engineering shears
   T Cu[24];
 #pragma unroll
@@ -113,14 +158,16 @@ __device__ __forceinline__ void constitutive(const HZ_GLB T* __restrict__ Cp, co
     }
     s[i] = acc;
   }
+  eigenstress<EIG>(M, ph, s);
 }
 
-// isotropic phase: sigma = lambda tr(eps) I + 2 mu eps
-template <typename T>
-__device__ __forceinline__ void constitutive_iso(T lam, T mu, const double* Eb, const T (&de)[6], T (&s)[6]) {
+// isotropic phase: sigma = lambda tr(eps) I + 2 mu eps - lambda:eps0
+template <bool EIG, typename T>
+__device__ __forceinline__ void constitutive_iso(T lam, T mu, const Mean<T>& M, int ph, const T (&de)[6],
+                                                 T (&s)[6]) {
   T e[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) e[c] = (T)Eb[c] + de[c];
+  for (int c = 0; c < 6; ++c) e[c] = M.Eb[c] + de[c];
   const T lt = lam * (e[0] + e[1] + e[2]), m2 = (T)2 * mu;
   s[0] = lt + m2 * e[0];
   s[1] = lt + m2 * e[1];
@@ -128,6 +175,7 @@ __device__ __forceinline__ void constitutive_iso(T lam, T mu, const double* Eb, 
   s[3] = m2 * e[3];
   s[4] = m2 * e[4];
   s[5] = m2 * e[5];
+  eigenstress<EIG>(M, ph, s);
 }
 
 // ----------------------------------------------------------------------------
@@ -219,13 +267,14 @@ __device__ __forceinline__ void xf_load(const XGeo& xg, const HZ_GLB cpx<T>* __r
 
 // last inverse pass -> constitutive law on the voxel pairs -> first forward pass.
 // Rounds of whole lines, so a round never reads what an earlier round wrote.
-template <typename T, bool ISO, int R>
+template <typename T, bool ISO, bool EIG, int R>
 __device__ __forceinline__ void xf_middle(const Desc& d, const XGeo& xg, cpx<T>* buf, const cpx<T>* twl,
                                           const HZ_GLB uint16_t* __restrict__ ph, double (&acc)[6]) {
   const int M = xg.M, LR = M / R, TY = xg.TY, H1p = xg.H1p;
   const int n = TY * LR;
   const int per = (kThreads / LR) * LR;
   const HZ_GLB T* C = glb(sizeof(T) == 8 ? reinterpret_cast<const T*>(d.C64) : reinterpret_cast<const T*>(d.C32));
+  const Mean<T> Mn = mean_state<T>(d);
 #pragma unroll 1
   for (int w0 = 0; w0 < n; w0 += per) {
     const int w = w0 + (int)threadIdx.x;
@@ -266,12 +315,12 @@ __device__ __forceinline__ void xf_middle(const Desc& d, const XGeo& xg, cpx<T>*
         }
         if (ISO) {
           const cpx<T> la = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + pa), lb = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + pb);
-          constitutive_iso<T>(la.x, la.y, d.Ebar, ea, sa);
-          constitutive_iso<T>(lb.x, lb.y, d.Ebar, eb, sb);
+          constitutive_iso<EIG, T>(la.x, la.y, Mn, pa, ea, sa);
+          constitutive_iso<EIG, T>(lb.x, lb.y, Mn, pb, eb, sb);
         } else {
-          constitutive<T>(C + pa * 24, d.Ebar, ea, sa);
+          constitutive<EIG, T>(C + pa * 24, Mn, pa, ea, sa);
           __builtin_amdgcn_sched_barrier(0);  // one stiffness row set live at a time
-          constitutive<T>(C + pb * 24, d.Ebar, eb, sb);
+          constitutive<EIG, T>(C + pb * 24, Mn, pb, eb, sb);
         }
 #pragma unroll
         for (int c = 0; c < 6; ++c) {

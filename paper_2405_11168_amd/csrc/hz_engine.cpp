@@ -10,7 +10,7 @@
 //   PS_IT64   plain FP64 iteration (eqs. basic_scheme_dep_2, tolerance)
 //   PS_R0     FP32 iterations of the full problem from u = 0 (first estimate)
 //   PS_SWEEP  one FP64 pass over the FP64 anchor U: measures eps, stores r
-//   PS_CORR   FP32 iterations on a correction delta with r added, Ebar = 0
+//   PS_CORR   FP32 iterations on a correction delta with r added, Ebar = 0, no eigenstress
 // In exact arithmetic the FP32 iterates of a correction round are the plain
 // scheme's iterates on U + delta, so the anchored scheme converges to the same
 // fixed point; the stop decision is always the FP64 sweep's residual.
@@ -301,6 +301,43 @@ void mandel(const double* C, double* M) {
     for (int j = 0; j < 6; ++j) M[i * 6 + j] = C[i * 6 + j] * s[i] * s[j];
 }
 
+namespace {
+// inverse of a 6x6 matrix by Gauss-Jordan elimination with partial pivoting
+bool invert6(const double* A, double* X) {
+  double a[6][12];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 12; ++j) a[i][j] = j < 6 ? A[i * 6 + j] : (j - 6 == i ? 1.0 : 0.0);
+  for (int c = 0; c < 6; ++c) {
+    int p = c;
+    for (int r = c + 1; r < 6; ++r)
+      if (std::fabs(a[r][c]) > std::fabs(a[p][c])) p = r;
+    if (!(std::fabs(a[p][c]) > 0)) return false;
+    if (p != c)
+      for (int j = 0; j < 12; ++j) std::swap(a[p][j], a[c][j]);
+    const double inv = 1.0 / a[c][c];
+    for (int j = 0; j < 12; ++j) a[c][j] *= inv;
+    for (int r = 0; r < 6; ++r)
+      if (r != c) {
+        const double f = a[r][c];
+        for (int j = 0; j < 12; ++j) a[r][j] -= f * a[c][j];
+      }
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) X[i * 6 + j] = a[i][j + 6];
+  return true;
+}
+
+// sigma (tensor comps) of an engineering Voigt stiffness C acting on a strain e (tensor comps)
+void voigt_apply(const double* C, const double* e, double* s) {
+  const double g[6] = {e[0], e[1], e[2], 2 * e[3], 2 * e[4], 2 * e[5]};
+  for (int i = 0; i < 6; ++i) {
+    double a = 0;
+    for (int j = 0; j < 6; ++j) a += C[i * 6 + j] * g[j];
+    s[i] = a;
+  }
+}
+}  // namespace
+
 void auto_reference(int np, const double* C, double* C0) {
   double lo = 1e300, hi = -1e300;
   for (int p = 0; p < np; ++p) {
@@ -331,6 +368,12 @@ Reference make_reference(const hz_opts& o, const Material& m) {
     if (!(e > 0)) fail(HZ_ENOTSPD, "reference medium is not positive definite");
   Reference r;
   voigt_to_tensor(C0, r.C0t);
+  // lambda0^-1 on tensor comps: eps = D^-1 M^-1 D sigma with D = diag(1,1,1,v2,v2,v2)
+  double Mi[36];
+  if (!invert6(M, Mi)) fail(HZ_ENOTSPD, "reference medium is singular");
+  const double sq[6] = {1, 1, 1, std::sqrt(2.0), std::sqrt(2.0), std::sqrt(2.0)};
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) r.S0[i * 6 + j] = Mi[i * 6 + j] * sq[j] / sq[i];
   r.iso = isotropic(C0, r.lam0, r.mu0) ? 1 : 0;
   return r;
 }
@@ -383,12 +426,44 @@ std::shared_ptr<Material> make_material(const Geo& geo, int n_phases, const doub
   }
   m->c32.resize(m->c64.size());
   for (size_t i = 0; i < m->c32.size(); ++i) m->c32[i] = (float)m->c64[i];
+  std::vector<long long> cnt(n_phases, 0);
+  for (long long i = 0; i < N; ++i) cnt[phase[i]]++;
+  m->frac.resize(n_phases);
+  for (int p = 0; p < n_phases; ++p) m->frac[p] = (double)cnt[p] / (double)N;
   return m;
 }
 
-size_t material_table_bytes(const Material& m) {
-  return align_up(m.c64.size() * 8) + align_up(m.c32.size() * 4) + align_up(m.phase.size() * 2);
+std::shared_ptr<Material> with_eigenstrain(const Material& src, const double* eps0) {
+  auto m = std::make_shared<Material>(src);
+  m->eig.clear();
+  m->tau64.clear();
+  m->tau32.clear();
+  std::fill(m->tau_mean, m->tau_mean + 6, 0.0);
+  if (!eps0) return m;
+  const int np = m->n_phases;
+  for (int i = 0; i < 6 * np; ++i)
+    if (!std::isfinite(eps0[i])) fail(HZ_EINVAL, "non-finite eigenstrain");
+  m->eig.assign(eps0, eps0 + 6 * (size_t)np);
+  m->tau64.assign((size_t)np * 8, 0.0);
+  for (int p = 0; p < np; ++p) {
+    double t[6];
+    voigt_apply(m->C.data() + 36 * (size_t)p, eps0 + 6 * (size_t)p, t);
+    for (int c = 0; c < 6; ++c) {
+      m->tau64[(size_t)p * 8 + c] = t[c];
+      m->tau_mean[c] += m->frac[p] * t[c];
+    }
+  }
+  m->tau32.resize(m->tau64.size());
+  for (size_t i = 0; i < m->tau32.size(); ++i) m->tau32[i] = (float)m->tau64[i];
+  return m;
 }
+
+size_t material_table_bytes(int np, long long N) {
+  return align_up((size_t)np * 24 * 8) + align_up((size_t)np * 24 * 4) + align_up((size_t)N * 2) +
+         align_up((size_t)np * 8 * 8) + align_up((size_t)np * 8 * 4);
+}
+
+size_t material_table_bytes(const Material& m) { return material_table_bytes(m.n_phases, (long long)m.phase.size()); }
 
 MaterialTables upload_material_tables(const Material& m, char* dev, hipStream_t st) {
   MaterialTables t{};
@@ -402,6 +477,16 @@ MaterialTables upload_material_tables(const Material& m, char* dev, hipStream_t 
   t.phase = reinterpret_cast<const uint16_t*>(dev + p);
   hip_check(hipMemcpyAsync(dev + p, m.phase.data(), m.phase.size() * 2, hipMemcpyHostToDevice, st),
             "upload phase map");
+  p += align_up(m.phase.size() * 2);
+  if (!m.tau64.empty()) {
+    t.tau64 = reinterpret_cast<const double*>(dev + p);
+    hip_check(hipMemcpyAsync(dev + p, m.tau64.data(), m.tau64.size() * 8, hipMemcpyHostToDevice, st),
+              "upload eigenstress");
+    p += align_up((size_t)m.n_phases * 8 * 8);
+    t.tau32 = reinterpret_cast<const float*>(dev + p);
+    hip_check(hipMemcpyAsync(dev + p, m.tau32.data(), m.tau32.size() * 4, hipMemcpyHostToDevice, st),
+              "upload eigenstress");
+  }
   hip_check(hipStreamSynchronize(st), "sync");
   return t;
 }
@@ -518,9 +603,10 @@ void pass_front(Engine& e, const Shape& sh, const ShapeTables& tb, const int* ac
 }
 
 // P3: x pass; with fields, T1 writes and T2 then adds its half of the averages.  The
-// active list holds the n_iso problems with all-isotropic materials first.
+// active list holds the problems ordered by material kind (KIND_ISO, KIND_EIG bits),
+// cnt[k] of kind k, each kind launched with its own instantiation.
 template <typename T>
-void pass_x(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso, int fields) {
+void pass_x(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt, int fields) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
@@ -533,13 +619,10 @@ void pass_x(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, i
       const Plan& pi = sh.plans[4];
       xg.rNI = recip(M / pi.radix[0] / 2 + 1);
       xg.rLRm = recip(M / pi.radix[pi.np - 1]);
-      if (n_iso > 0)
-        L.done(launch_xfused<T>(e.d_desc, act, n_iso, true, xg, tb.plans + 4, tb.plans + 5, tw[0], e.stream),
-               "x pass");
-      if (n > n_iso)
-        L.done(launch_xfused<T>(e.d_desc, act + n_iso, n - n_iso, false, xg, tb.plans + 4, tb.plans + 5, tw[0],
-                                e.stream),
-               "x pass");
+      for (int k = 0, off = 0; k < 4; off += cnt[k++])
+        if (cnt[k] > 0)
+          L.done(launch_xfused<T>(e.d_desc, act + off, cnt[k], k, xg, tb.plans + 4, tb.plans + 5, tw[0], e.stream),
+                 "x pass");
     } else {
       L.done(launch_xpass<T>(e.d_desc, act, n, xg, tb.plans + 3, tw[0], e.stream), "x pass");
     }
@@ -570,16 +653,16 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
 }
 
 template <typename T>
-void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso, int c0) {
+void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt, int c0) {
   pass_front<T>(e, sh, tb, act, n);
-  pass_x<T>(e, sh, tb, act, n, n_iso, 0);
+  pass_x<T>(e, sh, tb, act, n, cnt, 0);
   pass_back<T>(e, sh, tb, act, n, c0);
 }
 
 // the same iteration in the stencil form: 3-field transforms around the real-space
 // strain / constitutive / corner-force kernel
 template <typename T>
-void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int n_iso,
+void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt,
                        int c0) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
@@ -605,8 +688,8 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
   }
   {
     Launch L(e, K_STEN, d);
-    if (n_iso > 0) L.done(launch_stencil<T>(e.d_desc, act, n_iso, true, sh.sg, e.stream), "stencil");
-    if (n > n_iso) L.done(launch_stencil<T>(e.d_desc, act + n_iso, n - n_iso, false, sh.sg, e.stream), "stencil");
+    for (int k = 0, off = 0; k < 4; off += cnt[k++])
+      if (cnt[k] > 0) L.done(launch_stencil<T>(e.d_desc, act + off, cnt[k], k, sh.sg, e.stream), "stencil");
   }
   {
     const Plan& pf = sh.plans[5];
@@ -631,6 +714,11 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
 }
 
 bool kernel_fp64(PState s) { return s == PS_IT64 || s == PS_SWEEP; }
+
+// material kind in the problem's current state (a correction round has no eigenstress)
+int kind_of(const Prob* p) {
+  return (p->base.iso ? KIND_ISO : 0) | (p->base.tau64 && p->st != PS_CORR ? KIND_EIG : 0);
+}
 
 }  // namespace
 
@@ -703,7 +791,7 @@ void Engine::enter_state(Prob* p) {
   d.max_iters = p->max_iters;
   d.fixed_iters = p->fixed_iters;
   d.inner_max = p->inner_max;
-  for (int c = 0; c < 6; ++c) d.Ebar[c] = p->E[c];
+  for (int c = 0; c < 6; ++c) s[ST_EBAR + c] = p->Eb0[c];
   switch (p->st) {
     case PS_IT64:
       d.cmode = 0;
@@ -731,7 +819,10 @@ void Engine::enter_state(Prob* p) {
       d.cmode = 2;
       d.fmode = 2;
       d.src = 0;
-      for (int c = 0; c < 6; ++c) d.Ebar[c] = 0.0;
+      // the correction solves the linear part alone: no mean strain, no eigenstress
+      for (int c = 0; c < 6; ++c) s[ST_EBAR + c] = 0.0;
+      d.tau64 = nullptr;
+      d.tau32 = nullptr;
       // residual of U + delta is measured against the sweep's ||<sigma>||; the round
       // stops at rho times the sweep's residual (half of tol when that is below tol)
       s[ST_NORM] = p->sweep_norm;
@@ -756,7 +847,8 @@ std::vector<Prob*> Engine::tick() {
     int cat;  // 0 accumulate, 1 zero u0 FP64, 2 zero u0 FP32, 3 zero U, 4 iterate FP64, 5 iterate FP32
     const Prob* proto;
     std::vector<Prob*> ps;
-    int off = 0, K = 0, ev0 = 0, n_iso = 0;
+    int off = 0, K = 0, ev0 = 0;
+    int cnt[4]{};  // problems of each material kind, in kind order
   };
   std::vector<Seg> segs;
   auto put = [&](int cat, Prob* p) {
@@ -785,12 +877,12 @@ std::vector<Prob*> Engine::tick() {
     put(kernel_fp64(p->st) ? 4 : 5, p);
   }
   std::stable_sort(segs.begin(), segs.end(), [](const Seg& a, const Seg& b) { return a.cat < b.cat; });
-  // iterate groups list problems with all-isotropic materials first (the x pass has a
-  // kernel for each kind)
+  // iterate groups list their problems by material kind (the kernels that apply the
+  // constitutive law have an instantiation for each)
   for (auto& s : segs)
     if (s.cat >= 4) {
-      std::stable_partition(s.ps.begin(), s.ps.end(), [](const Prob* p) { return p->base.iso != 0; });
-      s.n_iso = (int)std::count_if(s.ps.begin(), s.ps.end(), [](const Prob* p) { return p->base.iso != 0; });
+      std::stable_sort(s.ps.begin(), s.ps.end(), [](const Prob* a, const Prob* b) { return kind_of(a) < kind_of(b); });
+      for (const Prob* p : s.ps) s.cnt[kind_of(p)]++;
     }
   int cur = 0;
   for (auto& s : segs) {
@@ -842,11 +934,11 @@ std::vector<Prob*> Engine::tick() {
       int c0 = 0;
       for (const Prob* q : s.ps) c0 |= q->base.c0_iso ? 1 : 2;
       if (s.cat == 4) {
-        if (st) iteration_stencil<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso, c0);
-        else iteration<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso, c0);
+        if (st) iteration_stencil<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.cnt, c0);
+        else iteration<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.cnt, c0);
       } else {
-        if (st) iteration_stencil<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso, c0);
-        else iteration<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.n_iso, c0);
+        if (st) iteration_stencil<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.cnt, c0);
+        else iteration<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.cnt, c0);
       }
       hip_check(hipEventRecord(event(nev++), stream), "hipEventRecord");
     }
@@ -914,6 +1006,7 @@ void Engine::advance(Prob* p, const double* s, const double* t_iter) {
       p->parity = (int)s[ST_PARITY];
       p->err = s[ST_ERR];
       for (int c = 0; c < 6; ++c) p->mean[c] = s[ST_MEAN + c];
+      for (int c = 0; c < 6; ++c) p->Ebar[c] = s[ST_EBAR + c];
       p->t_done = p->iters < (int)p->times.size() ? p->times[p->iters] : p->times.back();
       p->st = PS_DONE;
       return;
@@ -987,13 +1080,13 @@ void output_fields(Engine& e, Prob& p, double* eps_dev, double* sig_dev) {
   d.sig_out = sig_dev;
   d.trace = nullptr;
   d.trace_len = 0;
-  for (int c = 0; c < 6; ++c) d.Ebar[c] = p.E[c];
   d.cmode = 0;
   d.fmode = 0;
   d.src = p.prec == HZ_FP64 ? 0 : 1;  // the reported iterate: u_k, or the FP64 anchor U
   double* s = e.h_status + (size_t)p.slot * kStatusLen;
   std::fill(s, s + kStatusLen, 0.0);
   s[ST_K] = p.prec == HZ_FP64 ? p.parity : 0;  // selects the slot the expansion reads
+  for (int c = 0; c < 6; ++c) s[ST_EBAR + c] = p.Ebar[c];
   e.h_desc[p.slot] = d;
   e.h_active[0] = p.slot;
   hip_check(hipMemcpyAsync(e.d_desc + p.slot, e.h_desc + p.slot, sizeof(Desc), hipMemcpyHostToDevice, e.stream),
@@ -1003,7 +1096,9 @@ void output_fields(Engine& e, Prob& p, double* eps_dev, double* sig_dev) {
             "status H2D");
   hip_check(hipMemcpyAsync(e.d_active, e.h_active, 4, hipMemcpyHostToDevice, e.stream), "active H2D");
   pass_front<double>(e, *p.shape, p.tab, e.d_active, 1);
-  pass_x<double>(e, *p.shape, p.tab, e.d_active, 1, p.base.iso ? 1 : 0, 1);
+  int cnt[4]{};
+  cnt[(p.base.iso ? KIND_ISO : 0) | (p.base.tau64 ? KIND_EIG : 0)] = 1;
+  pass_x<double>(e, *p.shape, p.tab, e.d_active, 1, cnt, 1);
   hip_check(hipStreamSynchronize(e.stream), "sync");
   if (e.prof->on) e.prof->drain();
 }

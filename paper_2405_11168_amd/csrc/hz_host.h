@@ -22,7 +22,7 @@ hipError_t launch_yline(const Desc*, const int*, int, const YGeo&, const Plan*, 
 template <typename T>
 hipError_t launch_xpass(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
 template <typename T>
-hipError_t launch_xfused(const Desc*, const int*, int, bool, const XGeo&, const Plan*, const Plan*, const void*,
+hipError_t launch_xfused(const Desc*, const int*, int, int, const XGeo&, const Plan*, const Plan*, const void*,
                          hipStream_t);
 template <typename T>
 hipError_t launch_zcon(const Desc*, const int*, int, bool, int, const ZGeo&, const Plan*, const void*, const void*,
@@ -34,7 +34,7 @@ hipError_t launch_xc2r(const Desc*, const int*, int, const XGeo&, const Plan*, c
 template <typename T>
 hipError_t launch_xr2c(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
 template <typename T>
-hipError_t launch_stencil(const Desc*, const int*, int, bool, const SGeo&, hipStream_t);
+hipError_t launch_stencil(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
 hipError_t launch_finalize(const Desc*, const int*, int, const FinGeo&, hipStream_t);
 hipError_t launch_accumulate(const Desc*, const int*, int, long long, hipStream_t);
 hipError_t launch_zero(const Desc*, const int*, int, int, long long, hipStream_t);
@@ -92,19 +92,31 @@ struct Material {
   int iso = 0;                 // every phase isotropic: tables hold (lambda, mu)
   std::vector<double> c64;     // [n_phases][24]
   std::vector<float> c32;
+  std::vector<double> frac;    // volume fraction of each phase
+  // eigenstrains (empty: none)
+  std::vector<double> eig;     // [n_phases][6] eps0_p, tensor comps
+  std::vector<double> tau64;   // [n_phases][8] eigenstress lambda_p:eps0_p, tensor comps (2 pad)
+  std::vector<float> tau32;
+  double tau_mean[6]{};        // <lambda:eps0>
 };
 std::shared_ptr<Material> make_material(const Geo& geo, int n_phases, const double* C, const uint16_t* phase);
+// a copy of m with per-phase eigenstrains eps0[n_phases][6] (tensor comps); null clears them
+std::shared_ptr<Material> with_eigenstrain(const Material& m, const double* eps0);
 struct MaterialTables {
   const double* C64;
   const float* C32;
   const uint16_t* phase;
+  const double* tau64;  // null without eigenstrains
+  const float* tau32;
 };
+size_t material_table_bytes(int n_phases, long long N);
 size_t material_table_bytes(const Material& m);
 MaterialTables upload_material_tables(const Material& m, char* dev, hipStream_t st);
 
 // ---- reference medium
 struct Reference {
   double C0t[81];  // full tensor
+  double S0[36];   // lambda0^-1 acting on tensor comps (11,22,33,23,13,12), row-major
   int iso = 0;
   double lam0 = 0, mu0 = 0;
 };
@@ -159,7 +171,10 @@ struct Prob {
   ShapeTables tab{};
   int prec = HZ_FP64;
   int form = HZ_SCHEME_SPECTRAL;  // realisation of the iteration (same iterates either way)
-  double E[6]{};
+  int loading = HZ_LOAD_STRAIN;
+  double E[6]{};      // applied mean strain, or applied stress under HZ_LOAD_STRESS
+  double Eb0[6]{};    // mean strain of iterate 0: E, or lambda0^-1:sigma^a
+  double Ebar[6]{};   // mean strain of the reported iterate
   double tol = 1e-8;
   int max_iters = 2000, fixed_iters = -1, inner_max = 400;
   double rho = 1e-3;

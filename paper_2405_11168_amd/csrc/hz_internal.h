@@ -29,6 +29,10 @@ struct Geo {
   long long N;     // N1 * N2 * N3
 };
 
+// Material kind of a problem, which selects the instantiation of the kernels that
+// apply the constitutive law: every phase isotropic, and eigenstrains present.
+enum { KIND_ISO = 1, KIND_EIG = 2 };
+
 // Per-problem descriptor.  One launch serves many same-shape problems (load
 // cases of one grid, or requests of a serving group); blockIdx.y picks one.
 struct Desc {
@@ -44,11 +48,17 @@ struct Desc {
   double lam0, mu0;
   double* part_sig;      // [nbx][6] FP64 partial sums of (sigma^T1 + sigma^T2)/2
   double* part_res;      // [nbq] FP64 partial sums of w |r/2|^2
-  double* status;        // [16] device-side state, see St below
+  double* status;        // [kStatusLen] device-side state, see St below
   double* eps_out;       // optional real-space output fields [6][N] FP64
   double* sig_out;
   double* trace;         // optional [max_iters+1][7]: eps_k, <sigma>_k
-  double Ebar[6];        // applied mean strain (tensor comps); zero for a correction
+  const double* tau64;   // optional [n_phases][8] eigenstress lambda_p:eps0_p (tensor comps), or null
+  const float* tau32;    // same in FP32
+  double sig_a[6];       // applied stress (stress loading), tensor comps
+  double S0[36];         // stress loading: lambda0^-1 acting on tensor comps, row-major
+  double sref;           // stress loading: fixed stress scale of the stop rule
+  int loading;           // 0 applied mean strain, 1 applied stress (Sec. 2.5)
+  int pad0;
   double C0[81];         // reference medium, full 3x3x3x3 tensor
   double tol;
   int max_iters;
@@ -77,8 +87,11 @@ enum St {
   ST_NORM = 13,      // ||<sigma>|| used for the criterion
   ST_REF = 14,       // inner refinement: reference residual level to reach
   ST_BEST = 15,      // inner refinement: best residual seen
+  ST_EBAR = 16,      // 16..21 mean strain Ebar of the current iterate (tensor comps): the
+                     // applied strain, zero in a correction round, or under applied stress
+                     // the iterate of the loop on the mean strain (updated on the device)
 };
-constexpr int kStatusLen = 16;
+constexpr int kStatusLen = 24;
 
 // z pass geometry (expand + inverse z, or forward z + contraction): a tile is TX
 // adjacent h2 columns of one h1 plane, all N3 elements, 3 displacement components.

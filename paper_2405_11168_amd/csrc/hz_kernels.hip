@@ -6,7 +6,7 @@
 //               then the 12 strain comps eps^T1 = D~ (x)_s u, eps^T2 = D~2 (x)_s u
 //               formed in the mixed (h1, h2, l3) domain
 //   k_yline     inverse y (12 comps)
-//   k_xpass     per (l3, l2-tile): C2R along x, sigma = C(phase):(Ebar + eps), R2C along x,
+//   k_xpass     per (l3, l2-tile): C2R along x, sigma = C(phase):(Ebar + eps - eps0), R2C along x,
 //               FP64 partial sums of <sigma>
 //   k_yline     forward y
 //   k_zcon      r = sigma^T1.conj(D~) + sigma^T2.conj(D~2) formed in the mixed domain,
@@ -195,6 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
   __syncthreads();
   // 3) constitutive law on voxel pairs (2n, 2n+1): real / imaginary parts
   double acc[6] = {0, 0, 0, 0, 0, 0};
+  const Mean<T> Mn = mean_state<T>(d);
   for (int it = threadIdx.x; it < TY * M; it += kThreads) {
     const int r = fdiv(it, xg.rM), n = it - r * M;
     T ea[6], eb[6], sa[6], sb[6];
@@ -207,11 +208,15 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
     const int pa = ph[r * xg.N1 + 2 * n], pb = ph[r * xg.N1 + 2 * n + 1];
     if (d.iso) {
       const cpx<T> la = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + pa), lb = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + pb);
-      constitutive_iso<T>(la.x, la.y, d.Ebar, ea, sa);
-      constitutive_iso<T>(lb.x, lb.y, d.Ebar, eb, sb);
+      constitutive_iso<false, T>(la.x, la.y, Mn, pa, ea, sa);
+      constitutive_iso<false, T>(lb.x, lb.y, Mn, pb, eb, sb);
     } else {
-      constitutive<T>(C + pa * 24, d.Ebar, ea, sa);
-      constitutive<T>(C + pb * 24, d.Ebar, eb, sb);
+      constitutive<false, T>(C + pa * 24, Mn, pa, ea, sa);
+      constitutive<false, T>(C + pb * 24, Mn, pb, eb, sb);
+    }
+    if (Mn.tau) {
+      eigenstress<true>(Mn, pa, sa);
+      eigenstress<true>(Mn, pb, sb);
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -223,8 +228,8 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
       const long long Nn = (long long)xg.N1 * xg.N2 * xg.N3;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        const double e0 = 0.5 * ((double)d.Ebar[c] + (double)ea[c]);
-        const double e1 = 0.5 * ((double)d.Ebar[c] + (double)eb[c]);
+        const double e0 = 0.5 * ((double)Mn.Eb[c] + (double)ea[c]);
+        const double e1 = 0.5 * ((double)Mn.Eb[c] + (double)eb[c]);
         const double s0 = 0.5 * (double)sa[c], s1 = 0.5 * (double)sb[c];
         if (half == 0) {
           d.eps_out[c * Nn + vox] = e0; d.eps_out[c * Nn + vox + 1] = e1;
@@ -268,9 +273,10 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
   }
 }
 
-// ISO: every phase of the material is isotropic (separate instantiations keep the
-// register budget of each at two waves per SIMD in FP64)
-template <typename T, bool ISO>
+// ISO: every phase of the material is isotropic; EIG: the problem has eigenstrains
+// (separate instantiations keep the register budget of each at two waves per SIMD
+// in FP64)
+template <typename T, bool ISO, bool EIG>
 __global__ __launch_bounds__(kThreads) void k_xfused(const Desc* __restrict__ descs,
                                                      const int* __restrict__ active, XGeo xg,
                                                      const Plan* __restrict__ planXi,
@@ -279,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_xfused(const Desc* __restrict__ de
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[6 * 4];
   const Desc& d = descs[active[blockIdx.y]];
-  if (problem_done(d) || (d.iso != 0) != ISO) return;
+  if (problem_done(d) || (d.iso != 0) != ISO || (d.tau64 != nullptr) != EIG) return;
   const int tiles2 = xg.N2 / xg.TY;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int half = xg.half >= 0 ? xg.half : (tile & 1);
@@ -316,10 +322,10 @@ __global__ __launch_bounds__(kThreads) void k_xfused(const Desc* __restrict__ de
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const HZ_GLB uint16_t* ph = glb(d.phase) + row0 * xg.N1;
   switch (pi.radix[np - 1]) {
-    case 4: xf_middle<T, ISO, 4>(d, xg, buf, twl, ph, acc); break;
-    case 2: xf_middle<T, ISO, 2>(d, xg, buf, twl, ph, acc); break;
-    case 5: xf_middle<T, ISO, 5>(d, xg, buf, twl, ph, acc); break;
-    default: xf_middle<T, ISO, 3>(d, xg, buf, twl, ph, acc); break;
+    case 4: xf_middle<T, ISO, EIG, 4>(d, xg, buf, twl, ph, acc); break;
+    case 2: xf_middle<T, ISO, EIG, 2>(d, xg, buf, twl, ph, acc); break;
+    case 5: xf_middle<T, ISO, EIG, 5>(d, xg, buf, twl, ph, acc); break;
+    default: xf_middle<T, ISO, EIG, 3>(d, xg, buf, twl, ph, acc); break;
   }
   Ns = pf.radix[0];
 #pragma unroll 1
@@ -378,16 +384,25 @@ hipError_t launch_xpass(const Desc* descs, const int* active, int nact, const XG
 }
 
 template <typename T>
-hipError_t launch_xfused(const Desc* descs, const int* active, int nact, bool iso, const XGeo& xg,
+hipError_t launch_xfused(const Desc* descs, const int* active, int nact, int kind, const XGeo& xg,
                          const Plan* planXi, const Plan* planXf, const void* twN1, hipStream_t s) {
   const size_t shm = ((size_t)6 * xg.TY * xg.H1p + xg.N1) * sizeof(cpx<T>);
   dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY) * (xg.half >= 0 ? 1 : 2)), nact);
-  if (iso)
-    hipLaunchKernelGGL((k_xfused<T, true>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf,
-                       (const cpx<T>*)twN1);
-  else
-    hipLaunchKernelGGL((k_xfused<T, false>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf,
-                       (const cpx<T>*)twN1);
+  const cpx<T>* tw = (const cpx<T>*)twN1;
+  switch (kind) {
+    case KIND_ISO:
+      hipLaunchKernelGGL((k_xfused<T, true, false>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf, tw);
+      break;
+    case KIND_ISO | KIND_EIG:
+      hipLaunchKernelGGL((k_xfused<T, true, true>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf, tw);
+      break;
+    case 0:
+      hipLaunchKernelGGL((k_xfused<T, false, false>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf, tw);
+      break;
+    default:
+      hipLaunchKernelGGL((k_xfused<T, false, true>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf, tw);
+      break;
+  }
   return hipGetLastError();
 }
 
@@ -397,7 +412,7 @@ template hipError_t launch_yline<double>(const Desc*, const int*, int, const YGe
 template hipError_t launch_yline<float>(const Desc*, const int*, int, const YGeo&, const Plan*, const void*, bool, hipStream_t);
 template hipError_t launch_xpass<double>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
 template hipError_t launch_xpass<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
-template hipError_t launch_xfused<double>(const Desc*, const int*, int, bool, const XGeo&, const Plan*, const Plan*, const void*, hipStream_t);
-template hipError_t launch_xfused<float>(const Desc*, const int*, int, bool, const XGeo&, const Plan*, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xfused<double>(const Desc*, const int*, int, int, const XGeo&, const Plan*, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xfused<float>(const Desc*, const int*, int, int, const XGeo&, const Plan*, const Plan*, const void*, hipStream_t);
 
 }  // namespace hz

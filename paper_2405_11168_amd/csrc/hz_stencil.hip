@@ -130,8 +130,8 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ desc
 __device__ __forceinline__ int tet_of(int o) { return ((o & 1) + ((o >> 1) & 1) + ((o >> 2) & 1)) & 1 ? 0 : 1; }
 
 // sigma^T1 (s[0..5]) and sigma^T2 (s[6..11]) of one voxel from its 8 corners u8[o][j]
-template <typename T, bool ISO>
-__device__ __forceinline__ void stencil_sigma(const Desc& d, const HZ_GLB T* C, int ph, cpx<T> lm,
+template <typename T, bool ISO, bool EIG>
+__device__ __forceinline__ void stencil_sigma(const Mean<T>& Mn, const HZ_GLB T* C, int ph, cpx<T> lm,
                                               const T (&u8)[8][3], T (&s)[12]) {
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -157,9 +157,9 @@ __device__ __forceinline__ void stencil_sigma(const Desc& d, const HZ_GLB T* C, 
     e[5] = (T)0.5 * (G[0][1] + G[1][0]);
     T out[6];
     if (ISO) {
-      constitutive_iso<T>(lm.x, lm.y, d.Ebar, e, out);
+      constitutive_iso<EIG, T>(lm.x, lm.y, Mn, ph, e, out);
     } else {
-      constitutive<T>(C + ph * 24, d.Ebar, e, out);
+      constitutive<EIG, T>(C + ph * 24, Mn, ph, e, out);
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) s[6 * k + c] = out[c];
@@ -172,7 +172,7 @@ __device__ __forceinline__ void stencil_sigma(const Desc& d, const HZ_GLB T* C, 
 // of the voxel plane (one halo voxel on the + side in x and y), completes the
 // force of corner plane p-1 and starts that of corner plane p.  Corner plane p+1
 // is fetched into registers one step ahead, so its latency overlaps the work.
-template <typename T, bool ISO>
+template <typename T, bool ISO, bool EIG>
 __global__ __launch_bounds__(kThreads) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
                                                       SGeo sg) {
   constexpr int UX = kStX + 2, UY = kStY + 2, VX = kStX + 1, VY = kStY + 1;
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil(const Desc* __restrict__ d
   __shared__ T sb[12][VY][VX];
   __shared__ double red[6 * 4];
   const Desc& d = descs[active[blockIdx.y]];
-  if (problem_done(d) || (d.iso != 0) != ISO) return;
+  if (problem_done(d) || (d.iso != 0) != ISO || (d.tau64 != nullptr) != EIG) return;
   const int N1 = sg.N1, N2 = sg.N2, N3 = sg.N3;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = tile % sg.tx, byz = tile / sg.tx;
@@ -194,6 +194,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil(const Desc* __restrict__ d
   const HZ_GLB T* ur = reinterpret_cast<const HZ_GLB T*>(glb(reinterpret_cast<const cpx<T>*>(d.spec)) + 3 * S);
   HZ_GLB T* gr = reinterpret_cast<HZ_GLB T*>(glb(reinterpret_cast<cpx<T>*>(d.spec)) + 6 * S);
   const HZ_GLB T* C = glb(sizeof(T) == 8 ? reinterpret_cast<const T*>(d.C64) : reinterpret_cast<const T*>(d.C32));
+  const Mean<T> Mn = mean_state<T>(d);
   const HZ_GLB uint16_t* ph = glb(d.phase);
   const int tid = threadIdx.x;
   const int cx = tid % kStX, cy = tid / kStX;  // the corner this thread owns
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil(const Desc* __restrict__ d
         for (int j = 0; j < 3; ++j) u8[o][j] = ub[sl][(j * UY + iy) * UX + ix];
       }
       T s12[12];
-      stencil_sigma<T, ISO>(d, C, cph[k], clm[k], u8, s12);
+      stencil_sigma<T, ISO, EIG>(Mn, C, cph[k], clm[k], u8, s12);
 #pragma unroll
       for (int c = 0; c < 12; ++c) sb[c][vy][vx] = s12[c];
       if (vx < wx && vy < wy && p < z0 + wz) {
@@ -362,12 +363,14 @@ hipError_t launch_xr2c(const Desc* descs, const int* active, int nact, const XGe
 }
 
 template <typename T>
-hipError_t launch_stencil(const Desc* descs, const int* active, int nact, bool iso, const SGeo& sg, hipStream_t s) {
+hipError_t launch_stencil(const Desc* descs, const int* active, int nact, int kind, const SGeo& sg, hipStream_t s) {
   dim3 grid((unsigned)(sg.tx * sg.ty * sg.tz), nact);
-  if (iso)
-    hipLaunchKernelGGL((k_stencil<T, true>), grid, dim3(kThreads), 0, s, descs, active, sg);
-  else
-    hipLaunchKernelGGL((k_stencil<T, false>), grid, dim3(kThreads), 0, s, descs, active, sg);
+  switch (kind) {
+    case KIND_ISO: hipLaunchKernelGGL((k_stencil<T, true, false>), grid, dim3(kThreads), 0, s, descs, active, sg); break;
+    case KIND_ISO | KIND_EIG: hipLaunchKernelGGL((k_stencil<T, true, true>), grid, dim3(kThreads), 0, s, descs, active, sg); break;
+    case 0: hipLaunchKernelGGL((k_stencil<T, false, false>), grid, dim3(kThreads), 0, s, descs, active, sg); break;
+    default: hipLaunchKernelGGL((k_stencil<T, false, true>), grid, dim3(kThreads), 0, s, descs, active, sg); break;
+  }
   return hipGetLastError();
 }
 
@@ -377,7 +380,7 @@ template hipError_t launch_xc2r<double>(const Desc*, const int*, int, const XGeo
 template hipError_t launch_xc2r<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
 template hipError_t launch_xr2c<double>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
 template hipError_t launch_xr2c<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
-template hipError_t launch_stencil<double>(const Desc*, const int*, int, bool, const SGeo&, hipStream_t);
-template hipError_t launch_stencil<float>(const Desc*, const int*, int, bool, const SGeo&, hipStream_t);
+template hipError_t launch_stencil<double>(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
+template hipError_t launch_stencil<float>(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
 
 }  // namespace hz

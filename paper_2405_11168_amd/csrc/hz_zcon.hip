@@ -265,8 +265,13 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
   double m[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) m[c] = v[c] * fg.invN;
-  const double nrm = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2] +
-                          2.0 * (m[3] * m[3] + m[4] * m[4] + m[5] * m[5]));
+  // under applied stress the residual is measured against the fixed scale d.sref
+  // (||sigma^a||, or the eigenstress scale when no stress is applied) instead of
+  // ||<sigma>||, which tends to sigma^a
+  const bool stress = d.loading == 1;
+  const double nrm = stress ? d.sref
+                            : sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2] +
+                                   2.0 * (m[3] * m[3] + m[4] * m[4] + m[5] * m[5]));
   const double L2 = sqrt(v[6]);
   const double err = nrm > 0.0 ? L2 / nrm : L2;
   if (k < d.trace_len && d.trace) {
@@ -305,12 +310,37 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
     }
     return;
   }
-  const bool stop = d.fixed_iters >= 0 ? (k >= d.fixed_iters) : (err < d.tol);
+  bool conv = err < d.tol;
+  double mis[6];
+  if (stress) {
+    // the loop on the mean strain has converged too: <sigma> = sigma^a (eq. equi_epsilon_bar)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) mis[c] = d.sig_a[c] - m[c];
+    const double dm = sqrt(mis[0] * mis[0] + mis[1] * mis[1] + mis[2] * mis[2] +
+                           2.0 * (mis[3] * mis[3] + mis[4] * mis[4] + mis[5] * mis[5]));
+    conv = conv && dm <= d.tol * d.sref;
+  }
+  const bool stop = d.fixed_iters >= 0 ? (k >= d.fixed_iters) : conv;
   const bool bad = !(err == err) || isinf(err) || (k > 0 && err > 1e3 * s[ST_FIRST_ERR]);
   if (stop || bad || k >= d.max_iters) {
     s[ST_DONE] = bad ? 3.0 : (stop ? 1.0 : 2.0);
     s[ST_ITERS] = k;
     s[ST_PARITY] = parity;
+    return;
+  }
+  if (stress) {
+    // step 6 of Algorithm 1: since <lambda>:Ebar + <lambda:deps> - <lambda:eps0> is
+    // <sigma>_k, the update is Ebar <- Ebar + lambda0^-1:(sigma^a - <sigma>_k)
+    double e[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double a = s[ST_EBAR + i];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) a += d.S0[i * 6 + j] * mis[j];
+      e[i] = a;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) s[ST_EBAR + i] = e[i];
   }
 }
 

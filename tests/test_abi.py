@@ -108,3 +108,61 @@ def test_reference_medium_rule():
     C0 = hz.reference_medium(C)
     expect = np.diag([m, m, m, m / 2, m / 2, m / 2])
     assert np.abs(C0 - expect).max() < 1e-10 * m
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of hz_opts / hz_info have the C compiler's sizes and offsets."""
+    fields = {"hz_opts": [f[0] for f in _abi.hz_opts._fields_], "hz_info": [f[0] for f in _abi.hz_info._fields_]}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "hz.h"', "int main(void) {"]
+    for st, names in fields.items():
+        lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for n in names:
+            lines.append(f'  printf("{st}.{n} %zu\\n", offsetof({st}, {n}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for st, cls in (("hz_opts", _abi.hz_opts), ("hz_info", _abi.hz_info)):
+        assert int(out[st]) == ctypes.sizeof(cls), st
+        for n in fields[st]:
+            assert int(out[f"{st}.{n}"]) == getattr(cls, n).offset, (st, n)
+
+
+def test_eigenstrain_and_loading_validation():
+    lib = hz.lib()
+    g = hz.Grid(4, 4, 6)
+    e0 = np.zeros((2, 6))
+    with pytest.raises(hz.HzError) as e:
+        g.set_eigenstrain(e0)
+    assert e.value.code == _abi.HZ_ENOMATERIAL
+    C = np.stack([syn.isotropic_voigt(1, 0.3), syn.isotropic_voigt(2, 0.3)])
+    g.set_material(C, np.zeros((6, 4, 4), dtype=np.uint16))
+    with pytest.raises(hz.HzError) as e:
+        g.set_eigenstrain(np.zeros((3, 6)))  # one row per phase
+    assert e.value.code == _abi.HZ_EINVAL
+    e0[1, 2] = np.nan
+    with pytest.raises(hz.HzError) as e:
+        g.set_eigenstrain(e0)
+    assert e.value.code == _abi.HZ_EINVAL
+    e0[1, 2] = 0.01
+    g.set_eigenstrain(e0)
+    g.set_eigenstrain(None)
+    # option checks come before the workspace check, so they run without a device
+    E = np.zeros(6)
+    for prec, loading in ((hz.HZ_FP32_REFINE, hz.HZ_LOAD_STRESS), (hz.HZ_FP64, 7)):
+        o = hz._opts(precision=prec, loading=loading)
+        rc = lib.hz_solve(g._h, 1, E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(o), None, None,
+                          None, None)
+        assert rc == _abi.HZ_EINVAL, (prec, loading)
+    o = hz._opts(loading=hz.HZ_LOAD_STRESS)
+    Ce = np.zeros(36)
+    assert lib.hz_effective_stiffness(g._h, ctypes.byref(o), Ce.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      None) == _abi.HZ_EINVAL
+    g.set_eigenstrain(e0)
+    o = hz._opts()
+    assert lib.hz_effective_stiffness(g._h, ctypes.byref(o), Ce.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      None) == _abi.HZ_EINVAL
