@@ -81,6 +81,15 @@ typedef struct hz_grid_s* hz_grid;
  *   space, so only the 3 displacement and 3 force components are transformed
  *   (needs N1/2 with a power-of-two factor, see hz_scheme_available).
  * HZ_SCHEME_AUTO: the stencil form where available, else the spectral one. */
+#define HZ_SCHEME_AUTO 0
+#define HZ_SCHEME_SPECTRAL 1
+#define HZ_SCHEME_STENCIL 2
+#define HZ_SCHEME_STRAIN 3   /* the strain-based Algorithm 2: the 12 strain spectra are the iterate,
+                                updated by Gamma(q).r (eq. Lippmann_Schwinger_strain_3); the same
+                                iterates as Algorithm 1 at more bytes per iteration.  HZ_FP64 and
+                                hz_solve only; needs a workspace bound for 2 n_loads loads;
+                                hz_get_displacement is not available after it. */
+
 /* Loading (Sec. 2.3 and Sec. 2.5).  Under HZ_LOAD_STRESS the six numbers of a load
  * are the applied stress sigma^a; the run stops at the first iterate k with
  *   L2_k / s < tol  and  ||<sigma>_k - sigma^a|| <= tol * s
@@ -89,10 +98,6 @@ typedef struct hz_grid_s* hz_grid;
  * both vanish.  HZ_LOAD_STRESS needs HZ_FP64. */
 #define HZ_LOAD_STRAIN 0
 #define HZ_LOAD_STRESS 1
-
-#define HZ_SCHEME_AUTO 0
-#define HZ_SCHEME_SPECTRAL 1
-#define HZ_SCHEME_STENCIL 2
 
 typedef struct {
   double tol;               /* stop at the first iterate k with eps_k < tol (eq. tolerance)   */
@@ -106,7 +111,7 @@ typedef struct {
   double* trace_mean;       /* optional [n_loads][max_iters+1][6]: <sigma>_k                    */
   double inner_rho;         /* refinement: inner loop stops at rho * eps of its FP64 sweep      */
   int32_t inner_max;        /* refinement: cap on inner iterations per outer round              */
-  int32_t scheme;           /* HZ_SCHEME_AUTO, HZ_SCHEME_SPECTRAL or HZ_SCHEME_STENCIL           */
+  int32_t scheme;           /* HZ_SCHEME_AUTO, _SPECTRAL, _STENCIL or _STRAIN                     */
   int32_t loading;          /* HZ_LOAD_STRAIN (E is the mean strain) or HZ_LOAD_STRESS            */
 } hz_opts;
 

@@ -15,8 +15,8 @@ import numpy as np
 
 from . import _abi
 from ._abi import (HZ_EDIVERGED, HZ_FP32_REFINE, HZ_FP64, HZ_LOAD_STRAIN, HZ_LOAD_STRESS, HZ_NOT_CONVERGED, HZ_OK,
-                   HZ_PENDING, HZ_SCHEME_AUTO, HZ_SCHEME_SPECTRAL, HZ_SCHEME_STENCIL, HZ_STAGNATED, HzError, check,
-                   hz_info, hz_opts)
+                   HZ_PENDING, HZ_SCHEME_AUTO, HZ_SCHEME_SPECTRAL, HZ_SCHEME_STENCIL, HZ_SCHEME_STRAIN,
+                   HZ_STAGNATED, HzError, check, hz_info, hz_opts)
 
 __all__ = ["Grid", "Server", "SolveResult", "HZ_FP64", "HZ_FP32_REFINE", "HZ_LOAD_STRAIN", "HZ_LOAD_STRESS", "HzError",
            "reference_medium", "lib"]
@@ -149,6 +149,7 @@ class Grid:
         self._bound = (precision, n_loads)
 
     def _ensure(self, precision, n_loads):
+        """Bind a workspace for at least n_loads loads (the strain-based scheme asks for 2 n)."""
         b = self._bound
         if b is None or b[0] != precision or b[1] < n_loads:
             self.bind(precision, n_loads)
@@ -160,7 +161,7 @@ class Grid:
         """E: [n_loads, 6] applied mean strains, or applied stresses with loading=HZ_LOAD_STRESS."""
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
         nl = E.shape[0]
-        self._ensure(precision, nl)
+        self._ensure(precision, 2 * nl if scheme == HZ_SCHEME_STRAIN else nl)
         o = _opts(tol, max_iters, precision, C0, fixed_iters, check_every, inner_rho, inner_max, scheme, loading)
         T = (fixed_iters if fixed_iters >= 0 else max_iters) + 1
         tr = tm = None

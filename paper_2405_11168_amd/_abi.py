@@ -24,6 +24,7 @@ HZ_FP32_REFINE = 1
 HZ_SCHEME_AUTO = 0
 HZ_SCHEME_SPECTRAL = 1
 HZ_SCHEME_STENCIL = 2
+HZ_SCHEME_STRAIN = 3
 
 HZ_LOAD_STRAIN = 0
 HZ_LOAD_STRESS = 1

@@ -33,14 +33,15 @@ void check_opts(const hz_opts& o) {
   if (o.max_iters < 0 || o.max_iters > kTraceCap - 1) fail(HZ_EINVAL, "max_iters out of range [0, 4096]");
   if (o.fixed_iters > kTraceCap - 1) fail(HZ_EINVAL, "fixed_iters out of range");
   if (o.inner_max < 0 || o.inner_max > 100000) fail(HZ_EINVAL, "inner_max out of range");
-  if (o.scheme < HZ_SCHEME_AUTO || o.scheme > HZ_SCHEME_STENCIL) fail(HZ_EINVAL, "unknown scheme");
+  if (o.scheme < HZ_SCHEME_AUTO || o.scheme > HZ_SCHEME_STRAIN) fail(HZ_EINVAL, "unknown scheme");
+  if (o.scheme == HZ_SCHEME_STRAIN && o.precision != HZ_FP64) fail(HZ_EINVAL, "the strain-based scheme needs HZ_FP64");
   if (o.loading != HZ_LOAD_STRAIN && o.loading != HZ_LOAD_STRESS) fail(HZ_EINVAL, "unknown loading");
   if (o.loading == HZ_LOAD_STRESS && o.precision != HZ_FP64) fail(HZ_EINVAL, "applied stress needs HZ_FP64");
 }
 
 int pick_form(const Shape& sh, int scheme) {
   if (scheme == HZ_SCHEME_STENCIL && !sh.stencil) fail(HZ_EINVAL, "the stencil scheme needs N1/2 with a power-of-two factor");
-  if (scheme == HZ_SCHEME_SPECTRAL) return HZ_SCHEME_SPECTRAL;
+  if (scheme == HZ_SCHEME_SPECTRAL || scheme == HZ_SCHEME_STRAIN) return scheme;
   return sh.stencil ? HZ_SCHEME_STENCIL : HZ_SCHEME_SPECTRAL;
 }
 
@@ -230,6 +231,8 @@ int grid_solve(hz_grid g, int nl, const double* E, const hz_opts& o, double* sig
   for (int b = 0; b < nl; ++b) {
     const ProbBuffers pb = carve_prob(g->shape, g->prec, true, g->ws + g->off.probs + (size_t)b * g->off.pb);
     setup_prob(g->probs[b], b, &g->shape, g->tab, g->mtab, *g->mat, R, pb, E + 6 * b, o);
+    // the strain-based form keeps its 12 strain spectra in the block of load nl + b
+    if (g->probs[b].form == HZ_SCHEME_STRAIN) g->probs[b].base.state = g->ws + g->off.probs + (size_t)(nl + b) * g->off.pb;
   }
   g->last_prec = -1;
   e.start_clock();
@@ -535,6 +538,8 @@ int hz_solve(hz_grid g, int32_t n_loads, const double* E, const hz_opts* o, doub
   check_loads(E, n_loads);
   check_bound(g);
   if (n_loads > g->cap) fail(HZ_EWORKSPACE, "workspace bound for fewer loads");
+  if (o->scheme == HZ_SCHEME_STRAIN && 2 * n_loads > g->cap)
+    fail(HZ_EWORKSPACE, "the strain-based scheme needs a workspace bound for 2 n_loads loads");
   if (o->precision != g->prec) fail(HZ_EWORKSPACE, "workspace bound for another precision");
   return grid_solve(g, n_loads, E, *o, sigma_mean, eps_out, sig_out, info);
   HZ_GUARD_END
@@ -562,6 +567,7 @@ int hz_get_displacement(hz_grid g, int32_t load, double* out) {
   check_bound(g);
   if (g->last_prec < 0 || load < 0 || load >= (int)g->probs.size()) fail(HZ_EINVAL, "no such load in the last solve");
   const Prob& p = g->probs[load];
+  if (p.form == HZ_SCHEME_STRAIN) fail(HZ_EINVAL, "the strain-based scheme keeps strains, not the displacement");
   const size_t n = (size_t)3 * g->shape.geo.S;
   const void* src = p.prec == HZ_FP64 ? (p.parity ? p.base.u[1] : p.base.u[0]) : p.base.u64;
   hip_check(hipStreamSynchronize(g->stream), "sync");
@@ -573,7 +579,7 @@ int hz_get_displacement(hz_grid g, int32_t load, double* out) {
 int hz_scheme_available(hz_grid g, int32_t scheme) {
   HZ_GUARD_BEGIN
   if (!g) fail(HZ_EINVAL, "NULL handle");
-  if (scheme == HZ_SCHEME_SPECTRAL || scheme == HZ_SCHEME_AUTO) return 1;
+  if (scheme == HZ_SCHEME_SPECTRAL || scheme == HZ_SCHEME_AUTO || scheme == HZ_SCHEME_STRAIN) return 1;
   if (scheme == HZ_SCHEME_STENCIL) return g->shape.stencil ? 1 : 0;
   fail(HZ_EINVAL, "unknown scheme");
   HZ_GUARD_END
@@ -675,6 +681,7 @@ int hz_server_submit(hz_server s, hz_grid g, int32_t n_loads, const double* E, c
   check_opts(*o);
   pick_form(g->shape, o->scheme);
   if (o->precision == HZ_FP64 && o->fixed_iters >= 0) fail(HZ_EINVAL, "fixed_iters is not served");
+  if (o->scheme == HZ_SCHEME_STRAIN) fail(HZ_EINVAL, "the strain-based scheme is not served (hz_solve only)");
   check_loads(E, n_loads);
   if (n_loads > s->max_problems) fail(HZ_EWORKSPACE, "more loads than the server has slots");
   auto r = std::make_unique<Req>();

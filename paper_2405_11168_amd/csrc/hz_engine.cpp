@@ -31,7 +31,7 @@ namespace hz {
 
 const char* const kKindNames[K_COUNT] = {"zexpand", "yinv", "xpass", "yfwd", "zcontract", "finalize", "accumulate",
                                          "zero", "zexpand3", "yinv3", "xc2r", "stencil", "xr2c", "yfwd3",
-                                         "zcontract3"};
+                                         "zcontract3", "zstrain"};
 
 [[noreturn]] void fail(int code, const std::string& m) { throw HzError{code, m}; }
 
@@ -602,6 +602,25 @@ void pass_front(Engine& e, const Shape& sh, const ShapeTables& tb, const int* ac
   L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], true, e.stream), "y inverse");
 }
 
+// P1 of the strain-based form (apply the previous update to the strains, inverse z)
+// and P2
+template <typename T>
+void pass_front_strain(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n) {
+  const int d = sizeof(T) == 8;
+  const Geo& G = sh.geo;
+  const char* const* tw = d ? tb.tw64 : tb.tw32;
+  const ZGeo zg = zgeo(sh, d);
+  {
+    Launch L(e, K_ZSTRAIN, d);
+    L.done(launch_zstrain<T>(e.d_desc, act, n, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
+                             e.stream),
+           "z strain");
+  }
+  const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3, 0};
+  Launch L(e, K_YINV, d);
+  L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], true, e.stream), "y inverse");
+}
+
 // P3: x pass; with fields, T1 writes and T2 then adds its half of the averages.  The
 // active list holds the problems ordered by material kind (KIND_ISO, KIND_EIG bits),
 // cnt[k] of kind k, each kind launched with its own instantiation.
@@ -655,6 +674,16 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
 template <typename T>
 void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt, int c0) {
   pass_front<T>(e, sh, tb, act, n);
+  pass_x<T>(e, sh, tb, act, n, cnt, 0);
+  pass_back<T>(e, sh, tb, act, n, c0);
+}
+
+// the strain-based form (Algorithm 2): the strains are the iterate, the contraction
+// stores w = Omega r (cmode 3) and the next P1 applies it
+template <typename T>
+void iteration_strain(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt,
+                      int c0) {
+  pass_front_strain<T>(e, sh, tb, act, n);
   pass_x<T>(e, sh, tb, act, n, cnt, 0);
   pass_back<T>(e, sh, tb, act, n, c0);
 }
@@ -794,7 +823,7 @@ void Engine::enter_state(Prob* p) {
   for (int c = 0; c < 6; ++c) s[ST_EBAR + c] = p->Eb0[c];
   switch (p->st) {
     case PS_IT64:
-      d.cmode = 0;
+      d.cmode = p->form == HZ_SCHEME_STRAIN ? 3 : 0;
       d.fmode = 0;
       d.src = 0;
       d.trace = p->base.trace;
@@ -930,15 +959,18 @@ std::vector<Prob*> Engine::tick() {
     const int* act = d_active + s.off;
     const int n = (int)s.ps.size();
     for (int i = 0; i < s.K; ++i) {
-      const bool st = s.proto->form == HZ_SCHEME_STENCIL;
+      const int form = s.proto->form;
       int c0 = 0;
       for (const Prob* q : s.ps) c0 |= q->base.c0_iso ? 1 : 2;
+      const Shape& sh = *s.proto->shape;
+      const ShapeTables& tb = s.proto->tab;
       if (s.cat == 4) {
-        if (st) iteration_stencil<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.cnt, c0);
-        else iteration<double>(*this, *s.proto->shape, s.proto->tab, act, n, s.cnt, c0);
+        if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, c0);
+        else if (form == HZ_SCHEME_STRAIN) iteration_strain<double>(*this, sh, tb, act, n, s.cnt, c0);
+        else iteration<double>(*this, sh, tb, act, n, s.cnt, c0);
       } else {
-        if (st) iteration_stencil<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.cnt, c0);
-        else iteration<float>(*this, *s.proto->shape, s.proto->tab, act, n, s.cnt, c0);
+        if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, c0);
+        else iteration<float>(*this, sh, tb, act, n, s.cnt, c0);
       }
       hip_check(hipEventRecord(event(nev++), stream), "hipEventRecord");
     }
@@ -1095,7 +1127,8 @@ void output_fields(Engine& e, Prob& p, double* eps_dev, double* sig_dev) {
                            e.stream),
             "status H2D");
   hip_check(hipMemcpyAsync(e.d_active, e.h_active, 4, hipMemcpyHostToDevice, e.stream), "active H2D");
-  pass_front<double>(e, *p.shape, p.tab, e.d_active, 1);
+  if (p.form == HZ_SCHEME_STRAIN) pass_front_strain<double>(e, *p.shape, p.tab, e.d_active, 1);
+  else pass_front<double>(e, *p.shape, p.tab, e.d_active, 1);
   int cnt[4]{};
   cnt[(p.base.iso ? KIND_ISO : 0) | (p.base.tau64 ? KIND_EIG : 0)] = 1;
   pass_x<double>(e, *p.shape, p.tab, e.d_active, 1, cnt, 1);

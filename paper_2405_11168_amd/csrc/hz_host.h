@@ -28,6 +28,9 @@ template <typename T>
 hipError_t launch_zcon(const Desc*, const int*, int, bool, int, const ZGeo&, const Plan*, const void*, const void*,
                        const void*, const void*, hipStream_t);
 template <typename T>
+hipError_t launch_zstrain(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*,
+                          const void*, const void*, hipStream_t);
+template <typename T>
 hipError_t launch_zexp3(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
 template <typename T>
 hipError_t launch_xc2r(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
@@ -145,7 +148,7 @@ ProbBuffers carve_prob(const Shape& s, int prec, bool trace, char* dev);
 // ---- per-kernel timing with HIP events
 enum Kind {
   K_ZEXP, K_YINV, K_XPASS, K_YFWD, K_ZCON, K_FINAL, K_ACCUM, K_ZERO,
-  K_ZEXP3, K_YINV3, K_XC2R, K_STEN, K_XR2C, K_YFWD3, K_ZCON3, K_COUNT
+  K_ZEXP3, K_YINV3, K_XC2R, K_STEN, K_XR2C, K_YFWD3, K_ZCON3, K_ZSTRAIN, K_COUNT
 };
 extern const char* const kKindNames[K_COUNT];
 

@@ -40,6 +40,7 @@ struct Desc {
   void* u[2];            // displacement spectra (3 comps), ping-pong, kernel precision
   void* u64;             // refinement: FP64 anchor U (3 comps)
   void* r32;             // refinement: FP64-sweep residual stored in FP32 (3 comps)
+  void* state;           // strain-based form: the 12 strain spectra (the iterate), kernel precision
   const uint16_t* phase; // [N3][N2][N1]
   const double* C64;     // [n_phases][24] Voigt upper triangle (21 used), or (lambda, mu) pairs if iso
   const float* C32;      // same in FP32
@@ -64,7 +65,8 @@ struct Desc {
   int max_iters;
   int fixed_iters;
   int trace_len;
-  int cmode;             // contraction: 0 update u, 1 FP64 sweep (store r), 2 update with r32 added
+  int cmode;             // contraction: 0 update u, 1 FP64 sweep (store r), 2 update with r32 added,
+                         // 3 strain-based form: store w = Omega r in u[0] (applied to the strains next)
   int fmode;             // stop rule: 0 plain, 1 sweep (measure only), 2 correction round, 3 FP32 round 0
   int src;               // expansion source: 0 u[parity], 1 FP64 anchor u64
   int inner_max;         // iteration cap of FP32 rounds

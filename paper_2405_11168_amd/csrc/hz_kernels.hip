@@ -101,6 +101,84 @@ __global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ desc
 }
 
 // ----------------------------------------------------------------------------
+// P1 of the strain-based form (Algorithm 2): the iterate is the 12 strain spectra.
+// The contraction of the previous iteration left w = Omega r in u[0]; here
+//   eps^Tk <- eps^Tk - D~k (x)_s w      (Gamma.r = D (x)_s (Omega r), eq.
+//   Lippmann_Schwinger_strain_3; D~2 carries the sign of the T2 update)
+// is applied in q-space, the updated strains are stored back, and they are
+// transformed along z into the work spectra, 3 components at a time.
+// d.cmode 3 with k = 0 starts from zero strains; any other cmode (the output
+// pass) transforms the stored strains unchanged.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_zstrain(const Desc* __restrict__ descs,
+                                                      const int* __restrict__ active, ZGeo zg,
+                                                      const Plan* __restrict__ plan3,
+                                                      const cpx<T>* __restrict__ tw3T,
+                                                      const cpx<double>* __restrict__ tw1,
+                                                      const cpx<double>* __restrict__ tw2,
+                                                      const cpx<double>* __restrict__ tw3) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Desc& d = descs[active[blockIdx.y]];
+  if (problem_done(d)) return;
+  const int TX = zg.TX, N2 = zg.N2, N3 = zg.N3;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int h1 = tile / zg.tiles;
+  const int h2_0 = (tile % zg.tiles) * TX;
+  const int lines = 3 * TX;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* twl = buf + lines * N3;
+  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
+  const bool iter = d.cmode == 3;
+  const int k = (int)d.status[ST_K];
+  const bool fresh = iter && k == 0, apply = iter && k > 0;
+  const long long plane = (long long)h1 * N3 * N2 + h2_0;
+  HZ_GLB cpx<T>* st = glb(reinterpret_cast<cpx<T>*>(d.state)) + plane;
+  const HZ_GLB cpx<T>* wv = glb(reinterpret_cast<const cpx<T>*>(d.u[0])) + plane;
+  const LdsAcc<T> lds{buf, 1, lines};
+  const cpx<double> t1 = tw1[h1];
+  const int ne = TX * N3;
+#pragma unroll 1
+  for (int g = 0; g < 4; ++g) {
+    const int tet = g >> 1, c0 = (g & 1) * 3, f0 = tet * 6 + c0;  // first of this group's 3 fields
+    __syncthreads();  // twiddles, and the previous group's transform is done with the LDS lines
+    for (int e = threadIdx.x; e < ne; e += kThreads) {
+      const int h3 = fdiv(e, zg.rTX), col = e - h3 * TX;
+      const int o = h3 * N2 + col;
+      cpx<T> v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] = fresh ? cpx<T>{0, 0} : gld(st + (f0 + c) * zg.S + o);
+      if (apply) {
+        cpx<double> D1[3], D2[3];
+        symbols(t1, tw2[h2_0 + col], tw3[h3], D1, D2);
+        const cpx<double>* D = tet == 0 ? D1 : D2;
+        cpx<double> w[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) w[a] = to64(gld(wv + a * zg.S + o));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          // (D (x)_s w) in comps (11,22,33,23,13,12)
+          const int comp = c0 + c;
+          const int i = comp < 3 ? comp : (comp == 3 ? 1 : 0);
+          const int j = comp < 3 ? comp : (comp == 5 ? 1 : 2);
+          const cpx<double> s = comp < 3 ? D[i] * w[j] : scale(D[i] * w[j] + D[j] * w[i], 0.5);
+          v[c] = fr64<T>(to64(v[c]) - s);
+        }
+      }
+      if (iter) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gst(st + (f0 + c) * zg.S + o, v[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lds.put(c * TX + col, h3, v[c]);
+    }
+    __syncthreads();
+    const GblAcc<T> dst{glb(reinterpret_cast<cpx<T>*>(d.spec)) + plane + (long long)f0 * zg.S, (int)zg.S, TX, 1, N2};
+    fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, lds, dst);
+  }
+}
+
+// ----------------------------------------------------------------------------
 // y pass: TX contiguous rows of length N2; first radix pass straight from HBM,
 // last radix pass straight to HBM, twiddles in LDS.
 // ----------------------------------------------------------------------------
@@ -406,6 +484,18 @@ hipError_t launch_xfused(const Desc* descs, const int* active, int nact, int kin
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_zstrain(const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
+                          const void* tw3T, const void* tw1, const void* tw2, const void* tw3, hipStream_t s) {
+  const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
+  dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
+  hipLaunchKernelGGL(k_zstrain<T>, grid, dim3(kThreads), shm, s, descs, active, zg, plan3, (const cpx<T>*)tw3T,
+                     (const cpx<double>*)tw1, (const cpx<double>*)tw2, (const cpx<double>*)tw3);
+  return hipGetLastError();
+}
+
+template hipError_t launch_zstrain<double>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
+template hipError_t launch_zstrain<float>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, const void*, hipStream_t);
 template hipError_t launch_zexp<double>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, hipStream_t);
 template hipError_t launch_zexp<float>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*, const void*, hipStream_t);
 template hipError_t launch_yline<double>(const Desc*, const int*, int, const YGeo&, const Plan*, const void*, bool, hipStream_t);

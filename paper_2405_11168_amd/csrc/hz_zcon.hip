@@ -12,6 +12,7 @@ namespace hz {
 // d.cmode 0: u[1-p] = u[p] - Omega r      (p = current slot)
 // d.cmode 1: FP64 sweep of the anchor: store r in r32, no update
 // d.cmode 2: correction round: r += r32, u[1-p] = u[p] - Omega r
+// d.cmode 3: strain-based form: u[0] = Omega r (the next P1 applies it to the strains)
 // ----------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void sig_dot(const cpx<T> (&s)[6], const cpx<double>* c, cpx<double>* out) {
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
   const int MODE = d.cmode;
   const int p = cur_slot(d);
   const HZ_GLB cpx<T>* uin = glb(reinterpret_cast<const cpx<T>*>(d.u[p])) + plane;
-  HZ_GLB cpx<T>* uout = glb(reinterpret_cast<cpx<T>*>(d.u[1 - p])) + plane;
+  HZ_GLB cpx<T>* uout = glb(reinterpret_cast<cpx<T>*>(d.u[MODE == 3 ? 0 : 1 - p])) + plane;
   const HZ_GLB cpx<float>* r32in = glb(reinterpret_cast<const cpx<float>*>(d.r32)) + plane;
   HZ_GLB cpx<float>* r32out = glb(reinterpret_cast<cpx<float>*>(d.r32)) + plane;
   constexpr int CH = 4;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
       const int o = h3 * N2 + col;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if (MODE != 1) uv[i][c] = gld(uin + c * zg.S + o);
+        if (MODE == 0 || MODE == 2) uv[i][c] = gld(uin + c * zg.S + o);
         if (MODE == 2) rv[i][c] = gld(r32in + c * zg.S + o);
       }
     }
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
       for (int a = 0; a < 3; ++a) {
         const cpx<double> dw = {O[a][0] * r[0].x + O[a][1] * r[1].x + O[a][2] * r[2].x,
                                 O[a][0] * r[0].y + O[a][1] * r[1].y + O[a][2] * r[2].y};
-        gst(uout + a * zg.S + o, fr64<T>(to64(uv[i][a]) - dw));
+        gst(uout + a * zg.S + o, fr64<T>(MODE == 3 ? dw : to64(uv[i][a]) - dw));
       }
     }
   }
