@@ -65,13 +65,13 @@ def kernel_bytes(kind, S, N, nloads, csz):
         "zcontract": 18 * S * csz,       # read 12 stress spectra + u, write u
     }
     stencil = {                          # stencil form: 3 displacement / force fields
-        "zexpand3": 6 * S * csz,         # read u, write 3 fields
+        "zexpand3": 6 * S * csz,         # read u, write 3 fields (first iteration of a solve only)
         "yinv3": 6 * S * csz,
         "xc2r": 3 * S * csz + 3 * N * rsz,
         "stencil": 6 * N * rsz + 2 * N,  # read u (corners), write g, phase map
         "xr2c": 3 * N * rsz + 3 * S * csz,
         "yfwd3": 6 * S * csz,
-        "zcontract3": 9 * S * csz,       # read g and u, write u
+        "zcontract3": 12 * S * csz,      # read g and u, write u and its inverse z transform
     }
     table = {**spectral, **stencil}
     if kind not in table:
@@ -82,7 +82,7 @@ def kernel_bytes(kind, S, N, nloads, csz):
 def iteration_bytes(scheme, S, N, csz):
     """Algorithmic bytes of one iteration of one load (sum over its passes)."""
     kinds = (["zexpand", "yinv", "xpass", "yfwd", "zcontract"] if scheme == "spectral" else
-             ["zexpand3", "yinv3", "xc2r", "stencil", "xr2c", "yfwd3", "zcontract3"])
+             ["yinv3", "xc2r", "stencil", "xr2c", "yfwd3", "zcontract3"])
     return sum(kernel_bytes(k, S, N, 1, csz) for k in kinds)
 
 

@@ -692,12 +692,14 @@ void iteration_strain(Engine& e, const Shape& sh, const ShapeTables& tb, const i
 // strain / constitutive / corner-force kernel
 template <typename T>
 void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt,
-                       int c0) {
+                       int c0, bool front) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
   const ZGeo zg = zgeo(sh, d);
-  {
+  // the inverse z transform of u comes from the previous contraction, except at the
+  // first iteration of a state (front: some problem of the group is there)
+  if (front) {
     Launch L(e, K_ZEXP3, d);
     L.done(launch_zexp3<T>(e.d_desc, act, n, zg, tb.plans + 2, tw[2], e.stream), "z expand");
   }
@@ -964,12 +966,13 @@ std::vector<Prob*> Engine::tick() {
       for (const Prob* q : s.ps) c0 |= q->base.c0_iso ? 1 : 2;
       const Shape& sh = *s.proto->shape;
       const ShapeTables& tb = s.proto->tab;
+      const bool front = i == 0 && std::any_of(s.ps.begin(), s.ps.end(), [](const Prob* q) { return q->k0 == 0; });
       if (s.cat == 4) {
-        if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, c0);
+        if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, c0, front);
         else if (form == HZ_SCHEME_STRAIN) iteration_strain<double>(*this, sh, tb, act, n, s.cnt, c0);
         else iteration<double>(*this, sh, tb, act, n, s.cnt, c0);
       } else {
-        if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, c0);
+        if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, c0, front);
         else iteration<float>(*this, sh, tb, act, n, s.cnt, c0);
       }
       hip_check(hipEventRecord(event(nev++), stream), "hipEventRecord");

@@ -15,7 +15,9 @@ namespace hz {
 // 3 displacement and 3 force components go through the transforms.
 // ----------------------------------------------------------------------------
 
-// inverse z transform of u (3 comps): u(q) -> slot 0, layout [c][h1][l3][h2]
+// inverse z transform of u (3 comps): u(q) -> slot 0, layout [c][h1][l3][h2].
+// Only the first iteration of a state needs it: every contraction that updates u
+// also writes the inverse z transform of the new u into slot 0.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_zexp3(const Desc* __restrict__ descs, const int* __restrict__ active,
                                                     ZGeo zg, const Plan* __restrict__ plan3,
@@ -23,6 +25,7 @@ __global__ __launch_bounds__(kThreads) void k_zexp3(const Desc* __restrict__ des
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
+  if ((d.cmode == 0 || d.cmode == 2) && (int)d.status[ST_K] > 0) return;  // slot 0 is current
   const int TX = zg.TX, N2 = zg.N2, N3 = zg.N3;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int h1 = tile / zg.tiles;
@@ -172,8 +175,10 @@ __device__ __forceinline__ void stencil_sigma(const Mean<T>& Mn, const HZ_GLB T*
 // of the voxel plane (one halo voxel on the + side in x and y), completes the
 // force of corner plane p-1 and starts that of corner plane p.  Corner plane p+1
 // is fetched into registers one step ahead, so its latency overlaps the work.
+// The FP32 isotropic variant without eigenstrains is held to 5 waves per SIMD (96
+// VGPRs, no spills); the FP64 variants are held to 3 by their LDS (50 KB per block).
 template <typename T, bool ISO, bool EIG>
-__global__ __launch_bounds__(kThreads) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
+__global__ __launch_bounds__(kThreads, (sizeof(T) == 4 && ISO && !EIG) ? 5 : 1) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
                                                       SGeo sg) {
   constexpr int UX = kStX + 2, UY = kStY + 2, VX = kStX + 1, VY = kStY + 1;
   constexpr int UP = 3 * UY * UX;                      // corner values per plane

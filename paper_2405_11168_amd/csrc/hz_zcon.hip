@@ -210,9 +210,19 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
       for (int a = 0; a < 3; ++a) {
         const cpx<double> dw = {O[a][0] * r[0].x + O[a][1] * r[1].x + O[a][2] * r[2].x,
                                 O[a][0] * r[0].y + O[a][1] * r[1].y + O[a][2] * r[2].y};
-        gst(uout + a * zg.S + o, fr64<T>(MODE == 3 ? dw : to64(uv[i][a]) - dw));
+        const cpx<T> un = fr64<T>(MODE == 3 ? dw : to64(uv[i][a]) - dw);
+        gst(uout + a * zg.S + o, un);
+        // stencil form: the updated u replaces r in its LDS line (same element, same thread)
+        if (STENCIL) lds.put(a * TX + col, h3, un);
       }
     }
+  }
+  if (STENCIL && (MODE == 0 || MODE == 2)) {
+    // first step of the next iteration, on the lines already in LDS: the inverse z
+    // transform of the updated u into slot 0 (k_zexp3 then skips this problem)
+    __syncthreads();
+    const GblAcc<T> dst{glb(reinterpret_cast<cpx<T>*>(d.spec)) + plane, (int)zg.S, TX, 1, N2};
+    fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, lds, dst);
   }
   block_sum<1>(part, red);
   if (threadIdx.x == 0) d.part_res[tile] = part[0];
