@@ -113,6 +113,12 @@ typedef struct {
   int32_t inner_max;        /* refinement: cap on inner iterations per outer round              */
   int32_t scheme;           /* HZ_SCHEME_AUTO, _SPECTRAL, _STENCIL or _STRAIN                     */
   int32_t loading;          /* HZ_LOAD_STRAIN (E is the mean strain) or HZ_LOAD_STRESS            */
+  const double* u_init;     /* optional [n_loads][3][n1/2+1][n3][n2] complex (re,im) FP64 in the
+                               layout and phase convention of hz_get_displacement: iterate 0 is
+                               this displacement instead of 0 (resume from a checkpoint).  HZ_FP64,
+                               spectral or stencil scheme, hz_solve only; NULL: start from 0    */
+  const double* Ebar_init;  /* optional [n_loads][6]: under HZ_LOAD_STRESS, the mean strain of
+                               iterate 0 (hz_info.Ebar of the checkpoint); NULL: lambda0^-1:sigma^a */
 } hz_opts;
 
 typedef struct {
@@ -131,7 +137,7 @@ typedef struct {
 
 /* Fill *o with defaults: tol 1e-8, max_iters 2000, HZ_FP64, automatic reference,
  * fixed_iters -1, check_every 8, no traces, inner_rho 1e-3, inner_max 400,
- * HZ_SCHEME_AUTO, HZ_LOAD_STRAIN. */
+ * HZ_SCHEME_AUTO, HZ_LOAD_STRAIN, no initial guess. */
 void hz_default_opts(hz_opts* o);
 
 /* Create a grid handle for an n1 x n2 x n3 periodic cell (Sec. 2.1).

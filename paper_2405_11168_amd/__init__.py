@@ -57,6 +57,12 @@ def _opts(tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1, 
     return o
 
 
+def _outcome(rc):
+    """A solve's worst per-load status: a diverged load is an outcome (its info and
+    outputs are written), every other negative code an error."""
+    return rc if rc == HZ_EDIVERGED else check(rc)
+
+
 def _result(sm, infos, rc, **kw):
     return SolveResult(
         mean_sigma=sm,
@@ -157,8 +163,11 @@ class Grid:
     # -- solve -----------------------------------------------------------------
     def solve(self, E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1,
               fields=False, trace=False, check_every=8, inner_rho=1e-3, inner_max=400,
-              scheme=HZ_SCHEME_AUTO, loading=HZ_LOAD_STRAIN) -> SolveResult:
-        """E: [n_loads, 6] applied mean strains, or applied stresses with loading=HZ_LOAD_STRESS."""
+              scheme=HZ_SCHEME_AUTO, loading=HZ_LOAD_STRAIN, u_init=None, Ebar_init=None) -> SolveResult:
+        """E: [n_loads, 6] applied mean strains, or applied stresses with loading=HZ_LOAD_STRESS.
+        u_init: optional [n_loads, 3, N1/2+1, N3, N2] complex displacement of iterate 0 (as
+        returned by displacement()); Ebar_init: optional [n_loads, 6] mean strain of iterate 0
+        under applied stress.  Together they resume a solve from a checkpoint."""
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
         nl = E.shape[0]
         self._ensure(precision, 2 * nl if scheme == HZ_SCHEME_STRAIN else nl)
@@ -170,6 +179,17 @@ class Grid:
             tm = np.full((nl, T, 6), np.nan)
             o.trace_residual = _dptr(tr)
             o.trace_mean = _dptr(tm)
+        keep = []
+        if u_init is not None:
+            n1, n2, n3 = self.shape
+            u = np.asarray(u_init, dtype=np.complex128).reshape(nl, 3, n1 // 2 + 1, n3, n2)
+            ui = np.ascontiguousarray(np.stack([u.real, u.imag], axis=-1))
+            keep.append(ui)
+            o.u_init = _dptr(ui)
+        if Ebar_init is not None:
+            eb = np.ascontiguousarray(np.asarray(Ebar_init, dtype=np.float64).reshape(nl, 6))
+            keep.append(eb)
+            o.Ebar_init = _dptr(eb)
         sm = np.zeros((nl, 6))
         infos = (hz_info * nl)()
         n1, n2, n3 = self.shape
@@ -177,8 +197,8 @@ class Grid:
         if fields:
             eps = np.zeros((nl, 6, n3, n2, n1))
             sig = np.zeros((nl, 6, n3, n2, n1))
-        rc = check(lib().hz_solve(self._h, nl, _dptr(E), ctypes.byref(o), _dptr(sm),
-                                  _dptr(eps) if fields else None, _dptr(sig) if fields else None, infos))
+        rc = _outcome(lib().hz_solve(self._h, nl, _dptr(E), ctypes.byref(o), _dptr(sm),
+                                     _dptr(eps) if fields else None, _dptr(sig) if fields else None, infos))
         return _result(sm, infos, rc, trace_residual=tr, trace_mean=tm, eps=eps, sigma=sig)
 
     def effective_stiffness(self, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, **kw):
@@ -269,7 +289,7 @@ class Server:
         nl = self._nloads[rid]
         sm = np.zeros((nl, 6))
         infos = (hz_info * nl)()
-        rc = check(lib().hz_server_query(self._h, rid, _dptr(sm), infos))
+        rc = _outcome(lib().hz_server_query(self._h, rid, _dptr(sm), infos))
         if rc == HZ_PENDING:
             return None
         if release:

@@ -45,6 +45,8 @@ class hz_opts(ctypes.Structure):
         ("inner_max", c_int32),
         ("scheme", c_int32),
         ("loading", c_int32),
+        ("u_init", POINTER(c_double)),
+        ("Ebar_init", POINTER(c_double)),
     ]
 
 

@@ -37,6 +37,8 @@ void check_opts(const hz_opts& o) {
   if (o.scheme == HZ_SCHEME_STRAIN && o.precision != HZ_FP64) fail(HZ_EINVAL, "the strain-based scheme needs HZ_FP64");
   if (o.loading != HZ_LOAD_STRAIN && o.loading != HZ_LOAD_STRESS) fail(HZ_EINVAL, "unknown loading");
   if (o.loading == HZ_LOAD_STRESS && o.precision != HZ_FP64) fail(HZ_EINVAL, "applied stress needs HZ_FP64");
+  if ((o.u_init || o.Ebar_init) && (o.precision != HZ_FP64 || o.scheme == HZ_SCHEME_STRAIN))
+    fail(HZ_EINVAL, "an initial guess needs HZ_FP64 and the spectral or stencil scheme");
 }
 
 int pick_form(const Shape& sh, int scheme) {
@@ -52,7 +54,8 @@ void check_loads(const double* E, int n) {
 
 // one load case ready for the executor
 void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, const MaterialTables& mt,
-                const Material& m, const Reference& R, const ProbBuffers& b, const double* E, const hz_opts& o) {
+                const Material& m, const Reference& R, const ProbBuffers& b, const double* E, int load,
+                const hz_opts& o) {
   p = Prob{};
   p.slot = slot;
   p.shape = sh;
@@ -61,7 +64,9 @@ void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, cons
   p.form = pick_form(*sh, o.scheme);
   p.loading = o.loading;
   for (int c = 0; c < 6; ++c) p.E[c] = E[c];
-  if (o.loading == HZ_LOAD_STRESS) {
+  if (o.loading == HZ_LOAD_STRESS && o.Ebar_init) {
+    for (int c = 0; c < 6; ++c) p.Eb0[c] = o.Ebar_init[6 * (size_t)load + c];
+  } else if (o.loading == HZ_LOAD_STRESS) {
     // initial mean strain lambda0^-1:sigma^a (Algorithm 1)
     for (int i = 0; i < 6; ++i) {
       double a = 0;
@@ -72,6 +77,7 @@ void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, cons
     for (int c = 0; c < 6; ++c) p.Eb0[c] = E[c];
   }
   for (int c = 0; c < 6; ++c) p.Ebar[c] = p.Eb0[c];
+  if (o.u_init) p.u_init = o.u_init + (size_t)load * 6 * sh->geo.S;  // 3 S complex = 6 S doubles
   p.tol = o.tol;
   p.max_iters = o.max_iters;
   p.fixed_iters = o.precision == HZ_FP64 ? o.fixed_iters : -1;
@@ -230,7 +236,7 @@ int grid_solve(hz_grid g, int nl, const double* E, const hz_opts& o, double* sig
   g->probs.assign(nl, Prob{});
   for (int b = 0; b < nl; ++b) {
     const ProbBuffers pb = carve_prob(g->shape, g->prec, true, g->ws + g->off.probs + (size_t)b * g->off.pb);
-    setup_prob(g->probs[b], b, &g->shape, g->tab, g->mtab, *g->mat, R, pb, E + 6 * b, o);
+    setup_prob(g->probs[b], b, &g->shape, g->tab, g->mtab, *g->mat, R, pb, E + 6 * b, b, o);
     // the strain-based form keeps its 12 strain spectra in the block of load nl + b
     if (g->probs[b].form == HZ_SCHEME_STRAIN) g->probs[b].base.state = g->ws + g->off.probs + (size_t)(nl + b) * g->off.pb;
   }
@@ -403,7 +409,7 @@ void admit(hz_server s) {
       const ProbBuffers pb = carve_prob(r->se->shape, r->opts.precision, r->opts.precision == HZ_FP64,
                                         base + r->off + (size_t)b * r->pb);
       setup_prob(r->probs[b], slot, &r->se->shape, r->se->tab, r->me->tab, *r->mat, r->ref, pb, r->E.data() + 6 * b,
-                 r->opts);
+                 b, r->opts);
       r->probs[b].owner = r;
     }
     for (auto& p : r->probs) s->eng.add(&p);
@@ -682,6 +688,7 @@ int hz_server_submit(hz_server s, hz_grid g, int32_t n_loads, const double* E, c
   pick_form(g->shape, o->scheme);
   if (o->precision == HZ_FP64 && o->fixed_iters >= 0) fail(HZ_EINVAL, "fixed_iters is not served");
   if (o->scheme == HZ_SCHEME_STRAIN) fail(HZ_EINVAL, "the strain-based scheme is not served (hz_solve only)");
+  if (o->u_init || o->Ebar_init) fail(HZ_EINVAL, "initial guesses are not served (hz_solve only)");
   check_loads(E, n_loads);
   if (n_loads > s->max_problems) fail(HZ_EWORKSPACE, "more loads than the server has slots");
   auto r = std::make_unique<Req>();

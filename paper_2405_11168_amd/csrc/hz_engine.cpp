@@ -898,7 +898,14 @@ std::vector<Prob*> Engine::tick() {
     if (p->enter) {
       enter_state(p);
       dirty = true;
-      if (p->st == PS_IT64) put(1, p);
+      if (p->st == PS_IT64) {
+        if (p->u_init)  // resume: iterate 0 is the given displacement
+          hip_check(hipMemcpyAsync(p->base.u[0], p->u_init, (size_t)3 * p->shape->geo.S * 16, hipMemcpyHostToDevice,
+                                   stream),
+                    "initial displacement H2D");
+        else
+          put(1, p);
+      }
       if (p->st == PS_R0) {
         put(2, p);
         put(3, p);

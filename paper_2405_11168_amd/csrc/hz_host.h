@@ -178,6 +178,7 @@ struct Prob {
   double E[6]{};      // applied mean strain, or applied stress under HZ_LOAD_STRESS
   double Eb0[6]{};    // mean strain of iterate 0: E, or lambda0^-1:sigma^a
   double Ebar[6]{};   // mean strain of the reported iterate
+  const double* u_init = nullptr;  // host: displacement of iterate 0 (3 S complex FP64), or null
   double tol = 1e-8;
   int max_iters = 2000, fixed_iters = -1, inner_max = 400;
   double rho = 1e-3;

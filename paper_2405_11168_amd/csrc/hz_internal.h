@@ -88,7 +88,7 @@ enum St {
   ST_FIRST_ERR = 12, // eps_0 (divergence watchdog)
   ST_NORM = 13,      // ||<sigma>|| used for the criterion
   ST_REF = 14,       // inner refinement: reference residual level to reach
-  ST_BEST = 15,      // inner refinement: best residual seen
+  ST_BEST = 15,      // smallest residual seen (watchdog; inner refinement: best at a 32-step mark)
   ST_EBAR = 16,      // 16..21 mean strain Ebar of the current iterate (tensor comps): the
                      // applied strain, zero in a correction round, or under applied stress
                      // the iterate of the loop on the mean strain (updated on the device)

@@ -332,7 +332,13 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
     conv = conv && dm <= d.tol * d.sref;
   }
   const bool stop = d.fixed_iters >= 0 ? (k >= d.fixed_iters) : conv;
-  const bool bad = !(err == err) || isinf(err) || (k > 0 && err > 1e3 * s[ST_FIRST_ERR]);
+  // watchdog: NaN/Inf, growth to 1e3 times the first residual, or a residual back above
+  // the first one and 10 times the smallest seen (the iterates run away while <sigma>
+  // grows with them, so eps alone grows only slowly)
+  const double best = k == 0 ? err : fmin(s[ST_BEST], err);
+  s[ST_BEST] = best;
+  const bool bad = !(err == err) || isinf(err) ||
+                   (k > 0 && (err > 1e3 * s[ST_FIRST_ERR] || (err > s[ST_FIRST_ERR] && err > 10.0 * best)));
   if (stop || bad || k >= d.max_iters) {
     s[ST_DONE] = bad ? 3.0 : (stop ? 1.0 : 2.0);
     s[ST_ITERS] = k;

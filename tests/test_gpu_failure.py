@@ -1,0 +1,102 @@
+"""Failure detection, determinism and resume on the GPU path: the device-side watchdog
+(a reference medium too soft for the basic scheme diverges, as the oracle's iterates
+do), the iteration cap, bitwise reproducibility of repeated solves (a missing
+barrier in an LDS pass would show up as run-to-run differences), and resuming from a
+checkpointed displacement."""
+import numpy as np
+import pytest
+
+import hz_synth as syn
+import paper_2405_11168_amd as hz
+from oracle import tetra
+from test_gpu_parity import SCHEMES, random_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _first_runaway(h):
+    """First k where the watchdog fires on a residual history: growth to 1e3 times the
+    first residual, or back above the first and 10 times the smallest seen."""
+    best = h[0]
+    for k in range(1, len(h)):
+        best = min(best, h[k])
+        if h[k] > 1e3 * h[0] or (h[k] > h[0] and h[k] > 10 * best):
+            return k
+    return None
+
+
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_too_soft_reference_medium_is_reported_as_diverged(scheme):
+    """lambda0 = 0.2 lambda_max: the iterates run away (the oracle's too); the watchdog
+    stops the solve at the first iterate its rule flags, the same on both sides."""
+    shape = (16, 16, 16)
+    ph, C, _, E = random_problem(shape, 2, 60, "iso")
+    s = np.array([1, 1, 1, 2 ** .5, 2 ** .5, 2 ** .5])
+    top = max(np.linalg.eigvalsh(c * np.outer(s, s)).max() for c in C)
+    C0 = syn.isotropic_voigt(0.2 * top, 0.0)
+    g = hz.Grid(*shape)
+    g.set_material(C, ph)
+    r = g.solve(E, C0=C0, tol=1e-10, max_iters=2000, trace=True, scheme=scheme)
+    k = int(r.iters[0])
+    ref = tetra.basic_scheme(ph, C, C0, E[0], fixed_iters=40, keep_fields=False)
+    ko = _first_runaway(ref.history)
+    _say(f"  diverged at iterate {k} (oracle history flags {ko}): residual {r.residual[0]:.3e}, "
+         f"first {r.trace_residual[0, 0]:.3e}")
+    assert r.rc == hz.HZ_EDIVERGED and r.status[0] == hz.HZ_EDIVERGED
+    assert ko is not None and k == ko
+    assert np.max(np.abs(r.trace_residual[0, : k + 1] - ref.history[: k + 1]) / ref.history[: k + 1]) < 1e-10
+
+
+def test_iteration_cap_reports_not_converged():
+    ph, C, C0, E = random_problem((12, 10, 8), 3, 61, "aniso")
+    g = hz.Grid(12, 10, 8)
+    g.set_material(C, ph)
+    r = g.solve(E, C0=C0, tol=1e-14, max_iters=3, trace=True)
+    assert r.rc == hz.HZ_NOT_CONVERGED and r.status[0] == hz.HZ_NOT_CONVERGED
+    assert r.iters[0] == 3
+    ref = tetra.basic_scheme(ph, C, C0, E[0], fixed_iters=3, keep_fields=False)
+    assert abs(r.residual[0] - ref.history[3]) < 1e-10 * ref.history[3]
+    assert np.abs(r.mean_sigma[0] - ref.mean_sigma).max() < 1e-12 * np.abs(ref.mean_sigma).max()
+
+
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_repeated_solves_are_bitwise_identical(scheme):
+    """Fixed-order reductions and no atomics: two solves of the same loads give the
+    same bits for every load, including the fields."""
+    p = syn.boolean128(n=64, seed=7)
+    g = hz.Grid(*p.shape)
+    g.set_material(p.C, p.phase)
+    a = g.solve(p.loads[:3], C0=p.C0, fixed_iters=12, trace=True, fields=True, scheme=scheme)
+    b = g.solve(p.loads[:3], C0=p.C0, fixed_iters=12, trace=True, fields=True, scheme=scheme)
+    for name in ("mean_sigma", "trace_residual", "trace_mean", "eps", "sigma"):
+        assert np.array_equal(getattr(a, name), getattr(b, name)), name
+
+
+@pytest.mark.parametrize("loading", [hz.HZ_LOAD_STRAIN, hz.HZ_LOAD_STRESS], ids=["strain", "stress"])
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_resume_from_checkpoint_is_bitwise(scheme, loading):
+    """Checkpoint = the displacement of an iterate (and its mean strain under applied
+    stress); a solve started from it continues the same iterates bit for bit."""
+    shape = (16, 12, 10)
+    ph, C, C0, E = random_problem(shape, 3, 62, "aniso")
+    g = hz.Grid(*shape)
+    g.set_material(C, ph)
+    if loading == hz.HZ_LOAD_STRESS:
+        rng = np.random.default_rng(62)
+        e0 = rng.normal(size=(3, 6)) * 5e-3
+        e0[0] = 0.0
+        g.set_eigenstrain(e0)
+        E = np.array([[0.4, -0.1, 0.2, 0.05, -0.08, 0.12]])
+    kw = dict(C0=C0, scheme=scheme, loading=loading)
+    full = g.solve(E, fixed_iters=12, trace=True, fields=True, **kw)
+    a = g.solve(E, fixed_iters=7, **kw)
+    u7 = g.displacement(0)[None]
+    b = g.solve(E, fixed_iters=5, trace=True, fields=True, u_init=u7, Ebar_init=a.Ebar, **kw)
+    assert np.array_equal(b.trace_residual[0, :6], full.trace_residual[0, 7:13])
+    assert np.array_equal(b.trace_mean[0, :6], full.trace_mean[0, 7:13])
+    for name in ("mean_sigma", "Ebar", "eps", "sigma"):
+        assert np.array_equal(getattr(b, name), getattr(full, name)), name
