@@ -205,61 +205,82 @@ __device__ __forceinline__ cpx<T> r2c_merge(cpx<T> a, cpx<T> b, cpx<T> twk, T hs
   return scale((a + conjg(b)) - mul_i(twk * (a - conjg(b))), hs);
 }
 
-// load + split + first inverse radix pass; writes line positions j*R + m
+// load + split + first inverse radix pass; writes line positions j*R + m.
+// Butterfly j takes h1 = j + m LR and its split partners h1 = LR - j + m LR (the
+// Nyquist value h1 = M for j = 0); both sets are loaded before any arithmetic, and for
+// small radices a thread issues the loads of U butterflies at once, so several HBM
+// round trips overlap.
 template <typename T, int R, int NC = 6>
 __device__ __forceinline__ void xf_load(const XGeo& xg, const HZ_GLB cpx<T>* __restrict__ src, cpx<T>* buf,
                                         const cpx<T>* twl) {
+  constexpr int U = R <= 4 ? 2 : 1;
   const int M = xg.M, LR = M / R, TY = xg.TY, nI = LR / 2 + 1;
   const int n = NC * nI * TY;
   const int hs = xg.N3 * xg.N2;  // stride between h1 planes
 #pragma unroll 1
-  for (int w = threadIdx.x; w < n; w += kThreads) {
-    const int q = fdiv(w, xg.rTY), r = w - q * TY;
-    const int c = fdiv(q, xg.rNI), it = q - c * nI;
-    const HZ_GLB cpx<T>* s = src + c * xg.S + r;
-    cpx<T>* line = buf + (c * TY + r) * xg.H1p;
-    const int j = it, j2 = LR - it;
-    cpx<T> x[R];
+  for (int w0 = threadIdx.x; w0 < n; w0 += U * kThreads) {
+    cpx<T> x[U][R], y[U][R];
+    int jj[U], rr[U], cc[U];
 #pragma unroll
-    for (int m = 0; m < R; ++m) x[m] = gld(s + (j + m * LR) * hs);
-    if (it == 0) {
-      // positions m LR; partner of m >= 1 is R - m, partner of 0 is the Nyquist value X[M]
-      const cpx<T> xM = gld(s + M * hs);
-      cpx<T> z[R];
-      z[0] = c2r_split(x[0], xM, twl[0]);
+    for (int u = 0; u < U; ++u) {
+      const int w = w0 + u * kThreads;
+      jj[u] = -1;
+      if (w < n) {
+        const int q = fdiv(w, xg.rTY), r = w - q * TY;
+        const int c = fdiv(q, xg.rNI), it = q - c * nI;
+        const HZ_GLB cpx<T>* s = src + c * xg.S + r;
+        jj[u] = it;
+        rr[u] = r;
+        cc[u] = c;
 #pragma unroll
-      for (int m = 1; m < R; ++m) z[m] = c2r_split(x[m], x[R - m], twl[m * LR]);
-      Dft<T, R, true>::run(z);
+        for (int m = 0; m < R; ++m) x[u][m] = gld(s + (it + m * LR) * hs);
+        // partners: h1 = LR - it + m LR <= M (for it = 0, y[R-1] is the Nyquist value)
 #pragma unroll
-      for (int m = 0; m < R; ++m) line[m] = z[m];
-    } else if (j2 == j) {
-      // butterfly LR/2 is its own partner: m <-> R-1-m
-#pragma unroll
-      for (int m = 0; m < R / 2; ++m) {
-        const cpx<T> a = x[m], b = x[R - 1 - m];
-        x[m] = c2r_split(a, b, twl[j + m * LR]);
-        x[R - 1 - m] = c2r_split(b, a, twl[j + (R - 1 - m) * LR]);
+        for (int m = 0; m < R; ++m) y[u][m] = gld(s + (LR - it + m * LR) * hs);
       }
-      if (R & 1) x[R / 2] = c2r_split(x[R / 2], x[R / 2], twl[j + (R / 2) * LR]);
-      Dft<T, R, true>::run(x);
+    }
 #pragma unroll
-      for (int m = 0; m < R; ++m) line[j * R + m] = x[m];
-    } else {
-      cpx<T> y[R];
+    for (int u = 0; u < U; ++u) {
+      const int j = jj[u];
+      if (j < 0) continue;
+      const int j2 = LR - j;
+      cpx<T>* line = buf + (cc[u] * TY + rr[u]) * xg.H1p;
+      if (j == 0) {
+        // positions m LR; partner of m >= 1 is R - m, partner of 0 is the Nyquist value X[M]
+        cpx<T> z[R];
+        z[0] = c2r_split(x[u][0], y[u][R - 1], twl[0]);
 #pragma unroll
-      for (int m = 0; m < R; ++m) y[m] = gld(s + (j2 + m * LR) * hs);
+        for (int m = 1; m < R; ++m) z[m] = c2r_split(x[u][m], x[u][R - m], twl[m * LR]);
+        Dft<T, R, true>::run(z);
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const cpx<T> a = x[m], b = y[R - 1 - m];
-        x[m] = c2r_split(a, b, twl[j + m * LR]);
-        y[R - 1 - m] = c2r_split(b, a, twl[j2 + (R - 1 - m) * LR]);
-      }
-      Dft<T, R, true>::run(x);
-      Dft<T, R, true>::run(y);
+        for (int m = 0; m < R; ++m) line[m] = z[m];
+      } else if (j2 == j) {
+        // butterfly LR/2 is its own partner: m <-> R-1-m
+        cpx<T>* xv = x[u];
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        line[j * R + m] = x[m];
-        line[j2 * R + m] = y[m];
+        for (int m = 0; m < R / 2; ++m) {
+          const cpx<T> a = xv[m], b = xv[R - 1 - m];
+          xv[m] = c2r_split(a, b, twl[j + m * LR]);
+          xv[R - 1 - m] = c2r_split(b, a, twl[j + (R - 1 - m) * LR]);
+        }
+        if (R & 1) xv[R / 2] = c2r_split(xv[R / 2], xv[R / 2], twl[j + (R / 2) * LR]);
+        Dft<T, R, true>::run(x[u]);
+#pragma unroll
+        for (int m = 0; m < R; ++m) line[j * R + m] = x[u][m];
+      } else {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          const cpx<T> a = x[u][m], b = y[u][R - 1 - m];
+          x[u][m] = c2r_split(a, b, twl[j + m * LR]);
+          y[u][R - 1 - m] = c2r_split(b, a, twl[j2 + (R - 1 - m) * LR]);
+        }
+        Dft<T, R, true>::run(x[u]);
+        Dft<T, R, true>::run(y[u]);
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          line[j * R + m] = x[u][m];
+          line[j2 * R + m] = y[u][m];
+        }
       }
     }
   }

@@ -131,6 +131,34 @@ bool make_xplans(int M, Plan& inv, Plan& fwd) {
   return true;
 }
 
+// Factorisation of M = N1/2 for the stencil form's separate x transforms: the C2R
+// split sits in the first pass and the R2C merge in the last one, and those passes
+// hold both halves of a pair in registers, so they take the smallest power-of-two
+// radix (the inverse plan starts with it, the forward plan is its reverse).
+bool make_split_plans(int M, Plan& inv, Plan& fwd) {
+  const Plan p = make_plan(M);
+  std::vector<int> v(p.radix, p.radix + p.np);
+  auto pow2 = [](int r) { return r == 16 || r == 8 || r == 4 || r == 2; };
+  if (v.empty()) return false;
+  if (v.size() == 1) {  // two passes at least
+    if (v[0] == 16) v = {4, 4};
+    else if (v[0] == 8) v = {2, 4};
+    else if (v[0] == 4) v = {2, 2};
+    else return false;
+  }
+  int best = -1;
+  for (int i = 0; i < (int)v.size(); ++i)
+    if (pow2(v[i]) && (best < 0 || v[i] < v[best])) best = i;
+  if (best < 0) return false;
+  const int r = v[best];
+  v.erase(v.begin() + best);
+  v.insert(v.begin(), r);
+  inv = plan_of(v, M);
+  std::reverse(v.begin(), v.end());
+  fwd = plan_of(v, M);
+  return true;
+}
+
 }  // namespace
 
 void Shape::init(int n1, int n2, int n3) {
@@ -146,6 +174,7 @@ void Shape::init(int n1, int n2, int n3) {
   plans[2] = make_plan(G.N3);
   plans[3] = make_plan(G.N1 / 2);
   xfused = make_xplans(G.N1 / 2, plans[4], plans[5]);
+  const bool split = make_split_plans(G.N1 / 2, plans[6], plans[7]);
   // spectra are addressed with 32-bit offsets inside one load's 12 fields
   if (12 * G.S >= (1LL << 31)) fail(HZ_EINVAL, "grid too large");
   for (int d = 0; d < 2; ++d) {
@@ -175,12 +204,12 @@ void Shape::init(int n1, int n2, int n3) {
     nbx[d] = 2 * G.N3 * (G.N2 / tyx);
     nbq[d] = G.H1 * (G.N2 / tx);
     // 3-field x transforms of the stencil form
-    int ty3 = std::min(32, G.N2);
+    int ty3 = std::min(HZ_TY3_CAP, G.N2);
     auto x3_fits = [&](int t) { return (3 * t * hp + G.N1) * csz <= kLdsBytes && 3 * t * (G.N1 / 2) <= tile; };
     while (ty3 > 1 && (!x3_fits(ty3) || G.N2 % ty3)) --ty3;
     TY3[d] = x3_fits(ty3) ? ty3 : 0;
   }
-  stencil = xfused && TY3[0] > 0 && TY3[1] > 0;
+  stencil = xfused && split && TY3[0] > 0 && TY3[1] > 0;
   sg.N1 = G.N1;
   sg.N2 = G.N2;
   sg.N3 = G.N3;
@@ -712,10 +741,10 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
   XGeo xg{G.N1, G.N2, G.N3, G.H1, sh.H1p[d], sh.TY3[d], M, recip(sh.TY3[d]), recip(M / 2 + 1), recip(M),
           G.S, 1.0 / (double)G.N, 0, 0, 1.0f, 1.0f};
   {
-    const Plan& pi = sh.plans[4];
+    const Plan& pi = sh.plans[6];
     xg.rNI = recip(M / pi.radix[0] / 2 + 1);
     Launch L(e, K_XC2R, d);
-    L.done(launch_xc2r<T>(e.d_desc, act, n, xg, tb.plans + 4, tw[0], e.stream), "x c2r");
+    L.done(launch_xc2r<T>(e.d_desc, act, n, xg, tb.plans + 6, pi.radix[0], tw[0], e.stream), "x c2r");
   }
   {
     Launch L(e, K_STEN, d);
@@ -723,10 +752,10 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
       if (cnt[k] > 0) L.done(launch_stencil<T>(e.d_desc, act + off, cnt[k], k, sh.sg, e.stream), "stencil");
   }
   {
-    const Plan& pf = sh.plans[5];
+    const Plan& pf = sh.plans[7];
     xg.rNI = recip(M / pf.radix[pf.np - 1] / 2 + 1);
     Launch L(e, K_XR2C, d);
-    L.done(launch_xr2c<T>(e.d_desc, act, n, xg, tb.plans + 5, tw[0], e.stream), "x r2c");
+    L.done(launch_xr2c<T>(e.d_desc, act, n, xg, tb.plans + 7, pf.radix[pf.np - 1], tw[0], e.stream), "x r2c");
   }
   {
     const YGeo yg{G.N2, sh.TXy[d], (long long)3 * G.H1 * G.N3, 9 * G.S};

@@ -33,9 +33,9 @@ hipError_t launch_zstrain(const Desc*, const int*, int, const ZGeo&, const Plan*
 template <typename T>
 hipError_t launch_zexp3(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
 template <typename T>
-hipError_t launch_xc2r(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+hipError_t launch_xc2r(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template <typename T>
-hipError_t launch_xr2c(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+hipError_t launch_xr2c(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template <typename T>
 hipError_t launch_stencil(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
 hipError_t launch_finalize(const Desc*, const int*, int, const FinGeo&, hipStream_t);
@@ -50,6 +50,11 @@ struct HzError {
 [[noreturn]] void fail(int code, const std::string& m);
 void hip_check(hipError_t e, const char* what);
 
+// rows per block of the stencil form's 3-field x transforms, at most (compile-time tuning)
+#ifndef HZ_TY3_CAP
+#define HZ_TY3_CAP 32
+#endif
+
 constexpr int kTraceCap = 4097;        // iterates recorded per load (eps_k, <sigma>_k)
 constexpr int kLdsBytes = 65536 - 512;  // LDS budget of one work-group
 
@@ -60,7 +65,8 @@ bool factor_ok(int n);
 // ---- grid shape: transform plans and tile sizes of every pass, both precisions
 struct Shape {
   Geo geo{};
-  Plan plans[6]{};  // N1, N2, N3, N1/2, fused x pass: inverse and forward factorisations of N1/2
+  Plan plans[8]{};  // N1, N2, N3, N1/2, fused x pass: inverse and forward factorisations of N1/2,
+                    // stencil form's C2R / R2C x transforms: inverse and forward factorisations
   bool xfused = false;  // the x pass runs in its fused form (needs >= 2 radix passes of N1/2)
   int TXz[2]{}, TXy[2]{}, TYx[2]{}, H1p[2]{};  // [0] FP32 kernels, [1] FP64 kernels
   int nbx[2]{}, nbq[2]{};                      // partial-sum blocks of the x and z passes

@@ -43,9 +43,11 @@ __global__ __launch_bounds__(kThreads) void k_zexp3(const Desc* __restrict__ des
   fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, src, dst);
 }
 
-// C2R along x of u (slot 0 -> slot 3 real rows).  Uses the fused pass's
-// factorisation: split + first inverse pass, middle passes, last pass to HBM.
-template <typename T>
+// C2R along x of u (slot 0 -> slot 3 real rows): split + first inverse pass (the
+// smallest power-of-two radix of N1/2), middle passes, last pass to HBM.
+// R0: the plan's first radix (one instantiation each, so the register budget is that
+// of the radix actually used)
+template <typename T, int R0>
 __global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ descs, const int* __restrict__ active,
                                                    XGeo xg, const Plan* __restrict__ planXi,
                                                    const cpx<T>* __restrict__ twN1) {
@@ -65,15 +67,10 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ desc
   HZ_GLB cpx<T>* spec = glb(reinterpret_cast<cpx<T>*>(d.spec));
   const Plan& pi = *planXi;
   const int np = pi.np;
-  switch (pi.radix[0]) {
-    case 16: xf_load<T, 16, 3>(xg, spec + row0, buf, twl); break;
-    case 8: xf_load<T, 8, 3>(xg, spec + row0, buf, twl); break;
-    case 4: xf_load<T, 4, 3>(xg, spec + row0, buf, twl); break;
-    default: xf_load<T, 2, 3>(xg, spec + row0, buf, twl); break;
-  }
+  xf_load<T, R0, 3>(xg, spec + row0, buf, twl);
   __syncthreads();
   const LdsAcc<T> lds{buf, xg.H1p, 1};
-  int Ns = pi.radix[0];
+  int Ns = R0;
 #pragma unroll 1
   for (int p = 1; p < np - 1; ++p) {
     pass_any<T, emax<T>(), true>(pi.radix[p], M, Ns, 3 * TY, true, twl, 2, lds, lds, true, pi.rLR[p], pi.rNs[p], 0.f);
@@ -87,8 +84,9 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ desc
                                pi.rNs[np - 1], 0.f);
 }
 
-// R2C along x of the corner force g (slot 6 real rows -> slot 9), with 1/N
-template <typename T>
+// R2C along x of the corner force g (slot 6 real rows -> slot 9), with 1/N.
+// RL: the plan's last radix (the merge pass).
+template <typename T, int RL>
 __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ descs, const int* __restrict__ active,
                                                    XGeo xg, const Plan* __restrict__ planXf,
                                                    const cpx<T>* __restrict__ twN1) {
@@ -120,12 +118,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ desc
     __syncthreads();
     Ns *= pf.radix[p];
   }
-  switch (pf.radix[np - 1]) {
-    case 16: xf_store<T, 16, 3>(xg, spec + 9 * xg.S + row0, buf, twl); break;
-    case 8: xf_store<T, 8, 3>(xg, spec + 9 * xg.S + row0, buf, twl); break;
-    case 4: xf_store<T, 4, 3>(xg, spec + 9 * xg.S + row0, buf, twl); break;
-    default: xf_store<T, 2, 3>(xg, spec + 9 * xg.S + row0, buf, twl); break;
-  }
+  xf_store<T, RL, 3>(xg, spec + 9 * xg.S + row0, buf, twl);
 }
 
 // corner o in {0,-1}^3 coded as bits (bit a set: o_a = 0, clear: o_a = -1);
@@ -221,14 +214,15 @@ __global__ __launch_bounds__(kThreads, (sizeof(T) == 4 && ISO && !EIG) ? 5 : 1) 
       loff[k] = c * Nn + gy * N1 + gx;
     }
   }
-  // in-plane phase-map offsets of this thread's voxels
+  // this thread's voxels (in-tile coordinates) and their in-plane phase-map offsets
   const int nv = (wx + 1) * (wy + 1);
-  int voff[2];
+  int voff[2], vxs[2], vys[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const int v = tid + k * kThreads;
-    const int vy = v / (wx + 1), vx = v - vy * (wx + 1);
-    int gx = x0 + vx, gy = y0 + vy;
+    vys[k] = v / (wx + 1);
+    vxs[k] = v - vys[k] * (wx + 1);
+    int gx = x0 + vxs[k], gy = y0 + vys[k];
     while (gx >= N1) gx -= N1;
     while (gy >= N2) gy -= N2;
     voff[k] = gy * N1 + gx;
@@ -273,9 +267,8 @@ __global__ __launch_bounds__(kThreads, (sizeof(T) == 4 && ISO && !EIG) ? 5 : 1) 
     // sigma of voxel plane p over (wx+1) x (wy+1) voxels
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const int v = tid + k * kThreads;
-      if (v >= nv) continue;
-      const int vy = v / (wx + 1), vx = v - vy * (wx + 1);
+      if (tid + k * kThreads >= nv) continue;
+      const int vy = vys[k], vx = vxs[k];
       T u8[8][3];
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
@@ -350,20 +343,34 @@ hipError_t launch_zexp3(const Desc* descs, const int* active, int nact, const ZG
 }
 
 template <typename T>
-hipError_t launch_xc2r(const Desc* descs, const int* active, int nact, const XGeo& xg, const Plan* planXi,
+hipError_t launch_xc2r(const Desc* descs, const int* active, int nact, const XGeo& xg, const Plan* planXi, int r0,
                        const void* twN1, hipStream_t s) {
   const size_t shm = ((size_t)3 * xg.TY * xg.H1p + xg.N1) * sizeof(cpx<T>);
   dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY)), nact);
-  hipLaunchKernelGGL(k_xc2r<T>, grid, dim3(kThreads), shm, s, descs, active, xg, planXi, (const cpx<T>*)twN1);
+  const cpx<T>* tw = (const cpx<T>*)twN1;
+  switch (r0) {
+    case 16: hipLaunchKernelGGL((k_xc2r<T, 16>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, tw); break;
+    case 8: hipLaunchKernelGGL((k_xc2r<T, 8>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, tw); break;
+    case 4: hipLaunchKernelGGL((k_xc2r<T, 4>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, tw); break;
+    case 2: hipLaunchKernelGGL((k_xc2r<T, 2>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, tw); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_xr2c(const Desc* descs, const int* active, int nact, const XGeo& xg, const Plan* planXf,
+hipError_t launch_xr2c(const Desc* descs, const int* active, int nact, const XGeo& xg, const Plan* planXf, int rl,
                        const void* twN1, hipStream_t s) {
   const size_t shm = ((size_t)3 * xg.TY * xg.H1p + xg.N1) * sizeof(cpx<T>);
   dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY)), nact);
-  hipLaunchKernelGGL(k_xr2c<T>, grid, dim3(kThreads), shm, s, descs, active, xg, planXf, (const cpx<T>*)twN1);
+  const cpx<T>* tw = (const cpx<T>*)twN1;
+  switch (rl) {
+    case 16: hipLaunchKernelGGL((k_xr2c<T, 16>), grid, dim3(kThreads), shm, s, descs, active, xg, planXf, tw); break;
+    case 8: hipLaunchKernelGGL((k_xr2c<T, 8>), grid, dim3(kThreads), shm, s, descs, active, xg, planXf, tw); break;
+    case 4: hipLaunchKernelGGL((k_xr2c<T, 4>), grid, dim3(kThreads), shm, s, descs, active, xg, planXf, tw); break;
+    case 2: hipLaunchKernelGGL((k_xr2c<T, 2>), grid, dim3(kThreads), shm, s, descs, active, xg, planXf, tw); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -381,10 +388,10 @@ hipError_t launch_stencil(const Desc* descs, const int* active, int nact, int ki
 
 template hipError_t launch_zexp3<double>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
 template hipError_t launch_zexp3<float>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
-template hipError_t launch_xc2r<double>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
-template hipError_t launch_xc2r<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
-template hipError_t launch_xr2c<double>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
-template hipError_t launch_xr2c<float>(const Desc*, const int*, int, const XGeo&, const Plan*, const void*, hipStream_t);
+template hipError_t launch_xc2r<double>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
+template hipError_t launch_xc2r<float>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
+template hipError_t launch_xr2c<double>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
+template hipError_t launch_xr2c<float>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template hipError_t launch_stencil<double>(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
 template hipError_t launch_stencil<float>(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
 
