@@ -268,6 +268,20 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+    # context for the roofline: what a plain 1 GiB device-to-device copy reaches on this
+    # GPU (read + write bytes over time), next to the published 8 TB/s
+    x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    copy_gbps = 10 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9
+    del x, y
+    log(f"bench: device copy {copy_gbps:.0f} GB/s")
     log(f"bench: building workload boolean{a.n} (contrast 1e3, 6 loads)")
     p = syn.boolean128(n=a.n)
     N1, N2, N3 = p.shape
@@ -329,7 +343,7 @@ def main():
     roof = {"bound": "hbm", "kernel": f"{kind}_{prec}", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "bytes_per_launch": per_launch_bytes,
-            "avg_launch_ms": round(avg_s * 1e3, 4), "launches": cnt}
+            "avg_launch_ms": round(avg_s * 1e3, 4), "launches": cnt, "device_copy_GBps": round(copy_gbps, 1)}
     per_kernel = {k: {"ms_per_launch": round(v[2] / v[3], 4), "share": round(v[2] / sum(x[2] for x in kinds.values()), 3)}
                   for k, v in kinds.items()}
     # whole-iteration fraction: algorithmic bytes of one iteration of the scheme used

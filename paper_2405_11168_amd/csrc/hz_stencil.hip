@@ -125,59 +125,54 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ desc
 // T1 takes the corners with an even number of -1 offsets
 __device__ __forceinline__ int tet_of(int o) { return ((o & 1) + ((o >> 1) & 1) + ((o >> 2) & 1)) & 1 ? 0 : 1; }
 
-// sigma^T1 (s[0..5]) and sigma^T2 (s[6..11]) of one voxel from its 8 corners u8[o][j]
-template <typename T, bool ISO, bool EIG>
-__device__ __forceinline__ void stencil_sigma(const Mean<T>& Mn, const HZ_GLB T* C, int ph, cpx<T> lm,
-                                              const T (&u8)[8][3], T (&s)[12]) {
+// sigma^Tk of one voxel from the 4 corners of tetrahedron k (u4[i] = corner o_i of Tk)
+template <typename T, bool ISO, bool EIG, int K>
+__device__ __forceinline__ void stencil_sigma_k(const Mean<T>& Mn, const HZ_GLB T* C, int ph, cpx<T> lm,
+                                                const T (&u4)[4][3], T (&out)[6]) {
+  T G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  int i = 0;
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    T G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int o = 0; o < 8; ++o) {
+    if (tet_of(o) != K) continue;
+    const T w0 = (o & 1) ? (T)0.5 : (T)-0.5, w1 = (o & 2) ? (T)0.5 : (T)-0.5, w2 = (o & 4) ? (T)0.5 : (T)-0.5;
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      if (tet_of(o) != k) continue;
-      // w_i(o) = +1/2 if o_i = 0 (bit set), -1/2 if o_i = -1 (bit clear)
-      const T w0 = (o & 1) ? (T)0.5 : (T)-0.5, w1 = (o & 2) ? (T)0.5 : (T)-0.5, w2 = (o & 4) ? (T)0.5 : (T)-0.5;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        G[0][j] += w0 * u8[o][j];
-        G[1][j] += w1 * u8[o][j];
-        G[2][j] += w2 * u8[o][j];
-      }
+    for (int j = 0; j < 3; ++j) {
+      G[0][j] += w0 * u4[i][j];
+      G[1][j] += w1 * u4[i][j];
+      G[2][j] += w2 * u4[i][j];
     }
-    T e[6];
-    e[0] = G[0][0];
-    e[1] = G[1][1];
-    e[2] = G[2][2];
-    e[3] = (T)0.5 * (G[1][2] + G[2][1]);
-    e[4] = (T)0.5 * (G[0][2] + G[2][0]);
-    e[5] = (T)0.5 * (G[0][1] + G[1][0]);
-    T out[6];
-    if (ISO) {
-      constitutive_iso<EIG, T>(lm.x, lm.y, Mn, ph, e, out);
-    } else {
-      constitutive<EIG, T>(C + ph * 24, Mn, ph, e, out);
-    }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) s[6 * k + c] = out[c];
+    ++i;
   }
+  T e[6];
+  e[0] = G[0][0];
+  e[1] = G[1][1];
+  e[2] = G[2][2];
+  e[3] = (T)0.5 * (G[1][2] + G[2][1]);
+  e[4] = (T)0.5 * (G[0][2] + G[2][0]);
+  e[5] = (T)0.5 * (G[0][1] + G[1][0]);
+  if (ISO) constitutive_iso<EIG, T>(lm.x, lm.y, Mn, ph, e, out);
+  else constitutive<EIG, T>(C + ph * 24, Mn, ph, e, out);
 }
 
 // Strain, constitutive law and corner force in real space.  A block owns a
 // kStX x kStY column of corners over TZ planes and streams along z: at voxel
-// plane p the corner planes p-1 and p sit in LDS (ring of two), it computes sigma
-// of the voxel plane (one halo voxel on the + side in x and y), completes the
-// force of corner plane p-1 and starts that of corner plane p.  Corner plane p+1
+// plane p the corner planes p-1 and p sit in LDS (ring of two); for T1 and then T2
+// it computes sigma^Tk of the voxel plane (one halo voxel on the + side in x and y)
+// and the corners gather it, which completes the force of corner plane p-1 and
+// starts that of corner plane p.  Corner plane p+1
 // is fetched into registers one step ahead, so its latency overlaps the work.
-// The FP32 isotropic variant without eigenstrains is held to 5 waves per SIMD (96
-// VGPRs, no spills); the FP64 variants are held to 3 by their LDS (50 KB per block).
+// Occupancy: one tetrahedron's stresses in LDS at a time (35 KB per block in FP64)
+// lets 4 blocks share a CU; the register bounds below are the largest that compile
+// without spills (FP64: 4 waves per SIMD without eigenstrains, 3 with; FP32: 5 for
+// the isotropic variant without eigenstrains).
 template <typename T, bool ISO, bool EIG>
-__global__ __launch_bounds__(kThreads, (sizeof(T) == 4 && ISO && !EIG) ? 5 : 1) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
+__global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T) == 8 ? 3 : 1)) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
                                                       SGeo sg) {
   constexpr int UX = kStX + 2, UY = kStY + 2, VX = kStX + 1, VY = kStY + 1;
   constexpr int UP = 3 * UY * UX;                      // corner values per plane
   constexpr int NL = (UP + kThreads - 1) / kThreads;   // per thread
   __shared__ T ub[2][UP];                              // [slot][c][yy][xx]
-  __shared__ T sb[12][VY][VX];
+  __shared__ T sb[6][VY][VX];  // sigma of one tetrahedron at a time
   __shared__ double red[6 * 4];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d) || (d.iso != 0) != ISO || (d.tau64 != nullptr) != EIG) return;
@@ -263,51 +258,58 @@ __global__ __launch_bounds__(kThreads, (sizeof(T) == 4 && ISO && !EIG) ? 5 : 1) 
 #pragma unroll 1
   for (int p = z0; p <= z0 + wz; ++p) {
     const int cur = p & 1, prv = cur ^ 1;
-    __syncthreads();
-    // sigma of voxel plane p over (wx+1) x (wy+1) voxels
+    T g1[3] = {0, 0, 0}, g0[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      if (tid + k * kThreads >= nv) continue;
-      const int vy = vys[k], vx = vxs[k];
-      T u8[8][3];
+      __syncthreads();  // k = 0: plane p stashed; k = 1: the gather of tetrahedron 0 is done with sb
+      // sigma^Tk of voxel plane p over (wx+1) x (wy+1) voxels
 #pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        // bit a set: o_a = 0, clear: o_a = -1; corner (vx + o1, vy + o2) sits at (vx + o1 + 1, vy + o2 + 1)
-        const int ix = vx + ((o & 1) ? 1 : 0), iy = vy + ((o & 2) ? 1 : 0);
-        const int sl = (o & 4) ? cur : prv;
+      for (int sl = 0; sl < 2; ++sl) {
+        if (tid + sl * kThreads >= nv) continue;
+        const int vy = vys[sl], vx = vxs[sl];
+        T u4[4][3];
+        int i = 0;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) u8[o][j] = ub[sl][(j * UY + iy) * UX + ix];
-      }
-      T s12[12];
-      stencil_sigma<T, ISO, EIG>(Mn, C, cph[k], clm[k], u8, s12);
+        for (int o = 0; o < 8; ++o) {
+          if (tet_of(o) != k) continue;
+          const int ix = vx + ((o & 1) ? 1 : 0), iy = vy + ((o & 2) ? 1 : 0);
+          const int slot = (o & 4) ? cur : prv;
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sb[c][vy][vx] = s12[c];
-      if (vx < wx && vy < wy && p < z0 + wz) {
+          for (int j = 0; j < 3; ++j) u4[i][j] = ub[slot][(j * UY + iy) * UX + ix];
+          ++i;
+        }
+        T out[6];
+        if (k == 0) stencil_sigma_k<T, ISO, EIG, 0>(Mn, C, cph[sl], clm[sl], u4, out);
+        else stencil_sigma_k<T, ISO, EIG, 1>(Mn, C, cph[sl], clm[sl], u4, out);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sacc[c] += 0.5 * ((double)s12[c] + (double)s12[6 + c]);
-      }
-    }
-    __syncthreads();
-    if (own) {
-      // corner (cx, cy) receives sigma of voxel (cx - o1, cy - o2): offset -1 -> voxel +1
-      T g1[3] = {0, 0, 0}, g0[3] = {0, 0, 0};
+        for (int c = 0; c < 6; ++c) sb[c][vy][vx] = out[c];
+        if (vx < wx && vy < wy && p < z0 + wz) {
 #pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        const int k = tet_of(o);
-        const int vx = cx + ((o & 1) ? 0 : 1), vy = cy + ((o & 2) ? 0 : 1);
-        const T w0 = (o & 1) ? (T)0.5 : (T)-0.5, w1 = (o & 2) ? (T)0.5 : (T)-0.5, w2 = (o & 4) ? (T)0.5 : (T)-0.5;
-        const T s0 = sb[6 * k + 0][vy][vx], s1 = sb[6 * k + 1][vy][vx], s2 = sb[6 * k + 2][vy][vx];
-        const T s3 = sb[6 * k + 3][vy][vx], s4 = sb[6 * k + 4][vy][vx], s5 = sb[6 * k + 5][vy][vx];
-        const T f0 = s0 * w0 + s5 * w1 + s4 * w2;
-        const T f1 = s5 * w0 + s1 * w1 + s3 * w2;
-        const T f2 = s4 * w0 + s3 * w1 + s2 * w2;
-        // o3 = 0 (bit 2 set): voxel plane = corner plane p; o3 = -1: corner plane p - 1
-        if (o & 4) {
-          g0[0] += f0; g0[1] += f1; g0[2] += f2;
-        } else {
-          g1[0] += f0; g1[1] += f1; g1[2] += f2;
+          for (int c = 0; c < 6; ++c) sacc[c] += 0.5 * (double)out[c];
         }
       }
+      __syncthreads();
+      if (own) {
+        // corner (cx, cy) receives sigma^Tk of voxel (cx - o1, cy - o2) for o in Tk
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+          if (tet_of(o) != k) continue;
+          const int vx = cx + ((o & 1) ? 0 : 1), vy = cy + ((o & 2) ? 0 : 1);
+          const T w0 = (o & 1) ? (T)0.5 : (T)-0.5, w1 = (o & 2) ? (T)0.5 : (T)-0.5, w2 = (o & 4) ? (T)0.5 : (T)-0.5;
+          const T s0 = sb[0][vy][vx], s1 = sb[1][vy][vx], s2 = sb[2][vy][vx];
+          const T s3 = sb[3][vy][vx], s4 = sb[4][vy][vx], s5 = sb[5][vy][vx];
+          const T f0 = s0 * w0 + s5 * w1 + s4 * w2;
+          const T f1 = s5 * w0 + s1 * w1 + s3 * w2;
+          const T f2 = s4 * w0 + s3 * w1 + s2 * w2;
+          if (o & 4) {
+            g0[0] += f0; g0[1] += f1; g0[2] += f2;
+          } else {
+            g1[0] += f0; g1[1] += f1; g1[2] += f2;
+          }
+        }
+      }
+    }
+    if (own) {
       if (p > z0) {
         const int at = (p - 1) * NP + (y0 + cy) * N1 + (x0 + cx);
 #pragma unroll
