@@ -249,7 +249,7 @@ def main():
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU: multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py measures one GPU; runs on more than one GPU are not supported",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
 
