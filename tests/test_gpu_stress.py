@@ -181,3 +181,22 @@ def test_server_mixes_stress_eigenstrain_and_strain_requests_bitwise():
         g, load, C0, loading = reqs[i]
         rs = g.solve(load, C0=C0, tol=1e-9, loading=loading)
         assert np.array_equal(rs.mean_sigma, r.mean_sigma) and np.array_equal(rs.Ebar, r.Ebar)
+
+
+def test_full_size_boolean128_under_applied_stress_first_iterates():
+    """The 128^3 Boolean workload of the benchmark under an applied stress (stencil
+    form, six loads at once): iterates 0..2 of one load against the oracle."""
+    p = syn.boolean128()
+    g = hz.Grid(*p.shape)
+    g.set_material(p.C, p.phase)
+    loads = np.zeros((6, 6))
+    loads[:, :] = S_A[0]
+    loads[1:] *= np.arange(2, 7)[:, None]  # six different stress levels
+    K = 2
+    r = g.solve(loads, C0=p.C0, fixed_iters=K, trace=True, loading=hz.HZ_LOAD_STRESS)
+    ref = tetra.basic_scheme(p.phase, p.C, p.C0, loads[3], fixed_iters=K, stress=True, keep_fields=False)
+    eh = np.max(np.abs(r.trace_residual[3, : K + 1] - ref.history) / ref.history)
+    em = np.abs(r.trace_mean[3, : K + 1] - ref.mean_history).max() / np.abs(ref.mean_history).max()
+    eb = np.abs(r.Ebar[3] - ref.Ebar).max() / np.abs(ref.Ebar).max()
+    _say(f"  boolean128 stress: residual {eh:.2e} <sigma> {em:.2e} Ebar {eb:.2e}")
+    assert eh < 1e-10 and em < 1e-12 and eb < 1e-12
