@@ -184,3 +184,22 @@ def test_fp32_refine_ceff_within_1e6_of_converged_oracle(scheme):
     err = np.abs(Ce - Co).max() / np.abs(Co).max()
     _say(f"  refine C_eff rel err {err:.2e}")
     assert err < 1e-6
+
+
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_large_non_power_of_two_cell_first_iterates(scheme):
+    """The 192 x 192 x 320 cell (11.8 M voxels, radix 3 and 5 passes, narrow z tiles),
+    Boolean spheres to 25% with contrast 1e2: iterates 0..1 against the oracle."""
+    p = syn.sphere_contrast((192, 192, 320), 1e2)
+    g = hz.Grid(*p.shape)
+    g.set_material(p.C, p.phase)
+    if not g.scheme_available(scheme):
+        pytest.skip(f"scheme {scheme} not available")
+    K = 1
+    E = p.loads[:1]
+    r = g.solve(E, C0=p.C0, fixed_iters=K, trace=True, scheme=scheme)
+    ref = tetra.basic_scheme(p.phase, p.C, p.C0, E[0], fixed_iters=K, keep_fields=False)
+    eh = np.max(np.abs(r.trace_residual[0, : K + 1] - ref.history) / ref.history)
+    em = np.abs(r.trace_mean[0, : K + 1] - ref.mean_history).max() / np.abs(ref.mean_history).max()
+    _say(f"  192x192x320: residual hist {eh:.2e} <sigma> {em:.2e}")
+    assert eh < 1e-10 and em < 1e-12
