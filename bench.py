@@ -65,13 +65,13 @@ def kernel_bytes(kind, S, N, nloads, csz):
         "zcontract": 18 * S * csz,       # read 12 stress spectra + u, write u
     }
     stencil = {                          # stencil form: 3 displacement / force fields
-        "zexpand3": 6 * S * csz,         # read u, write 3 fields (first iteration of a solve only)
-        "yinv3": 6 * S * csz,
+        "zconvert3": 6 * S * csz,        # u(q) <-> mixed domain in place (once per solve)
+        "yinv3": 6 * S * csz,            # read the mixed-domain u, write 3 fields
         "xc2r": 3 * S * csz + 3 * N * rsz,
         "stencil": 6 * N * rsz + 2 * N,  # read u (corners), write g, phase map
         "xr2c": 3 * N * rsz + 3 * S * csz,
         "yfwd3": 6 * S * csz,
-        "zcontract3": 12 * S * csz,      # read g and u, write u and its inverse z transform
+        "zcontract3": 9 * S * csz,       # read g and the mixed-domain u, write u
     }
     table = {**spectral, **stencil}
     if kind not in table:

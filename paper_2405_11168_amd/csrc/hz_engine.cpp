@@ -30,7 +30,7 @@
 namespace hz {
 
 const char* const kKindNames[K_COUNT] = {"zexpand", "yinv", "xpass", "yfwd", "zcontract", "finalize", "accumulate",
-                                         "zero", "zexpand3", "yinv3", "xc2r", "stencil", "xr2c", "yfwd3",
+                                         "zero", "zconvert3", "yinv3", "xc2r", "stencil", "xr2c", "yfwd3",
                                          "zcontract3", "zstrain"};
 
 [[noreturn]] void fail(int code, const std::string& m) { throw HzError{code, m}; }
@@ -718,22 +718,18 @@ void iteration_strain(Engine& e, const Shape& sh, const ShapeTables& tb, const i
 }
 
 // the same iteration in the stencil form: 3-field transforms around the real-space
-// strain / constitutive / corner-force kernel
+// strain / constitutive / corner-force kernel.  The displacement state is held in the
+// mixed domain (inverse z transform of u(q)): the iteration starts with the inverse y
+// transform of the state and the contraction updates the state in that domain.
 template <typename T>
 void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt,
-                       int c0, bool front) {
+                       int c0) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
   const ZGeo zg = zgeo(sh, d);
-  // the inverse z transform of u comes from the previous contraction, except at the
-  // first iteration of a state (front: some problem of the group is there)
-  if (front) {
-    Launch L(e, K_ZEXP3, d);
-    L.done(launch_zexp3<T>(e.d_desc, act, n, zg, tb.plans + 2, tw[2], e.stream), "z expand");
-  }
   {
-    const YGeo yg{G.N2, sh.TXy[d], (long long)3 * G.H1 * G.N3, 0};
+    const YGeo yg{G.N2, sh.TXy[d], (long long)3 * G.H1 * G.N3, 0, 1};
     Launch L(e, K_YINV3, d);
     L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], true, e.stream), "y inverse");
   }
@@ -840,6 +836,11 @@ void Engine::add(Prob* p) {
   live.push_back(p);
 }
 
+void Engine::convert_stencil_state(void* u, const Prob& p, bool inverse) {
+  Launch L(*this, K_ZCONV3, 1);
+  L.done(launch_zconv3(u, inverse, zgeo(*p.shape, 1), p.tab.plans + 2, p.tab.tw64[2], stream), "z convert");
+}
+
 void Engine::enter_state(Prob* p) {
   Desc d = p->base;
   d.status = d_status + (size_t)p->slot * kStatusLen;
@@ -928,12 +929,14 @@ std::vector<Prob*> Engine::tick() {
       enter_state(p);
       dirty = true;
       if (p->st == PS_IT64) {
-        if (p->u_init)  // resume: iterate 0 is the given displacement
+        if (p->u_init) {  // resume: iterate 0 is the given displacement
           hip_check(hipMemcpyAsync(p->base.u[0], p->u_init, (size_t)3 * p->shape->geo.S * 16, hipMemcpyHostToDevice,
                                    stream),
                     "initial displacement H2D");
-        else
+          if (p->form == HZ_SCHEME_STENCIL) convert_stencil_state(p->base.u[0], *p, true);
+        } else {
           put(1, p);
+        }
       }
       if (p->st == PS_R0) {
         put(2, p);
@@ -1002,13 +1005,12 @@ std::vector<Prob*> Engine::tick() {
       for (const Prob* q : s.ps) c0 |= q->base.c0_iso ? 1 : 2;
       const Shape& sh = *s.proto->shape;
       const ShapeTables& tb = s.proto->tab;
-      const bool front = i == 0 && std::any_of(s.ps.begin(), s.ps.end(), [](const Prob* q) { return q->k0 == 0; });
       if (s.cat == 4) {
-        if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, c0, front);
+        if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, c0);
         else if (form == HZ_SCHEME_STRAIN) iteration_strain<double>(*this, sh, tb, act, n, s.cnt, c0);
         else iteration<double>(*this, sh, tb, act, n, s.cnt, c0);
       } else {
-        if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, c0, front);
+        if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, c0);
         else iteration<float>(*this, sh, tb, act, n, s.cnt, c0);
       }
       hip_check(hipEventRecord(event(nev++), stream), "hipEventRecord");
@@ -1038,8 +1040,13 @@ std::vector<Prob*> Engine::tick() {
       if (p->st == PS_DONE) fin.push_back(p);
     }
   }
-  // FP64 traces of the problems that finished
+  // a finished stencil-form problem reports u(q): its iterate leaves the mixed domain
+  for (Prob* p : fin)
+    if (p->form == HZ_SCHEME_STENCIL)
+      convert_stencil_state(p->prec == HZ_FP64 ? p->base.u[p->parity & 1] : p->base.u64, *p, false);
   bool copied = false;
+  if (prof->on && !fin.empty()) copied = true;  // the synchronisation below lets the conversions' events drain
+  // FP64 traces of the problems that finished
   for (Prob* p : fin)
     if (p->base.trace && p->prec == HZ_FP64) {
       const int ntr = std::min(p->iters + 1, kTraceCap);
@@ -1049,6 +1056,7 @@ std::vector<Prob*> Engine::tick() {
       copied = true;
     }
   if (copied) hip_check(hipStreamSynchronize(stream), "sync");
+  if (prof->on) prof->drain();
   for (Prob* p : fin)
     if (!p->trace.empty())
       for (int t = 0; t * 7 < (int)p->trace.size() && t < (int)p->times.size(); ++t)

@@ -30,8 +30,8 @@ hipError_t launch_zcon(const Desc*, const int*, int, bool, int, const ZGeo&, con
 template <typename T>
 hipError_t launch_zstrain(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, const void*,
                           const void*, const void*, hipStream_t);
-template <typename T>
-hipError_t launch_zexp3(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
+// stencil-form displacement (FP64, in place): u(q) -> mixed domain (inverse) or back
+hipError_t launch_zconv3(void* u, bool inverse, const ZGeo&, const Plan*, const void*, hipStream_t);
 template <typename T>
 hipError_t launch_xc2r(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template <typename T>
@@ -154,7 +154,7 @@ ProbBuffers carve_prob(const Shape& s, int prec, bool trace, char* dev);
 // ---- per-kernel timing with HIP events
 enum Kind {
   K_ZEXP, K_YINV, K_XPASS, K_YFWD, K_ZCON, K_FINAL, K_ACCUM, K_ZERO,
-  K_ZEXP3, K_YINV3, K_XC2R, K_STEN, K_XR2C, K_YFWD3, K_ZCON3, K_ZSTRAIN, K_COUNT
+  K_ZCONV3, K_YINV3, K_XC2R, K_STEN, K_XR2C, K_YFWD3, K_ZCON3, K_ZSTRAIN, K_COUNT
 };
 extern const char* const kKindNames[K_COUNT];
 
@@ -239,6 +239,8 @@ struct Engine {
  private:
   hipEvent_t event(size_t i);
   void enter_state(Prob* p);
+  // stencil-form iterate u (FP64) in place: u(q) -> mixed domain (inverse) or back
+  void convert_stencil_state(void* u, const Prob& p, bool inverse);
   void advance(Prob* p, const double* s, const double* t_iter);
 };
 

@@ -108,11 +108,16 @@ struct YGeo {
   int N2, TX;
   long long nlines;                 // fields * H1 * N3
   long long off;                    // first line's element offset in the spectra (complex elements)
+  int from_state;                   // 1: read the lines from the problem's displacement state
+                                    // (stencil form), write them to the spectra at off
 };
 
-// Stencil form (same iterates as the Fourier form, eqs. DA1-DA2 in real space):
-// spectra slots of one load, in complex elements of the 12-field buffer:
-//   0..2  u: inverse z then inverse y, half spectrum along x       [3][h1][l3][l2]
+// Stencil form (same iterates as the Fourier form, eqs. DA1-DA2 in real space).
+// Its displacement state u[] (and the FP64 anchor) is held in the mixed domain
+// [3][h1][l3][h2] (inverse z transform of u(q)); it is converted from u(q) when a
+// solve starts from a given displacement and back to u(q) when a problem finishes.
+// Spectra slots of one load, in complex elements of the 12-field buffer:
+//   0..2  u: inverse y of the mixed-domain state, half spectrum along x  [3][h1][l3][l2]
 //   3..5  u on the corner grid, real                                [3][l3][l2][l1]
 //   6..8  corner force g = sum_T sigma^T(c - o) . w(o), real        [3][l3][l2][l1]
 //   9..11 g: forward x (1/N) then forward y                         [3][h1][l3][h2]

@@ -196,7 +196,13 @@ __global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ des
   for (int i = threadIdx.x; i < N2; i += kThreads) twl[i] = tw2T[i];
   const LdsAcc<T> lds{buf, N2, 1};
   const GblAcc<T> g{glb(reinterpret_cast<cpx<T>*>(d.spec)) + yg.off + t0 * N2, N2, 1, 0, 1};
-  fft_lines<T, emax<T>(), INV>(*plan2, lines, 0.f, true, twl, 1, lds, g, g);
+  if (yg.from_state) {
+    void* st = d.src == 1 ? d.u64 : d.u[cur_slot(d)];
+    const GblAcc<T> src{glb(reinterpret_cast<cpx<T>*>(st)) + t0 * N2, N2, 1, 0, 1};
+    fft_lines<T, emax<T>(), INV>(*plan2, lines, 0.f, true, twl, 1, lds, src, g);
+  } else {
+    fft_lines<T, emax<T>(), INV>(*plan2, lines, 0.f, true, twl, 1, lds, g, g);
+  }
 }
 
 // ----------------------------------------------------------------------------

@@ -15,32 +15,39 @@ namespace hz {
 // 3 displacement and 3 force components go through the transforms.
 // ----------------------------------------------------------------------------
 
-// inverse z transform of u (3 comps): u(q) -> slot 0, layout [c][h1][l3][h2].
-// Only the first iteration of a state needs it: every contraction that updates u
-// also writes the inverse z transform of the new u into slot 0.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_zexp3(const Desc* __restrict__ descs, const int* __restrict__ active,
-                                                    ZGeo zg, const Plan* __restrict__ plan3,
-                                                    const cpx<T>* __restrict__ tw3T) {
+// The iteration keeps a stencil-form displacement (3 comps, FP64) in the mixed domain
+// [3][h1][l3][h2]: its inverse z transform.  Conversion in place, one tile of TX
+// columns of one h1 plane per block: INV, u(q) -> mixed domain (a solve that starts
+// from a given displacement); otherwise mixed domain -> u(q), the forward transform
+// scaled by 1/N3 (a finished problem's reported iterate).
+template <bool INV>
+__global__ __launch_bounds__(kThreads) void k_zconv3(cpx<double>* __restrict__ u, ZGeo zg,
+                                                     const Plan* __restrict__ plan3,
+                                                     const cpx<double>* __restrict__ tw3, double scale) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const Desc& d = descs[active[blockIdx.y]];
-  if (problem_done(d)) return;
-  if ((d.cmode == 0 || d.cmode == 2) && (int)d.status[ST_K] > 0) return;  // slot 0 is current
   const int TX = zg.TX, N2 = zg.N2, N3 = zg.N3;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int h1 = tile / zg.tiles;
   const int h2_0 = (tile % zg.tiles) * TX;
   const int lines = 3 * TX;
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* twl = buf + lines * N3;
-  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
+  cpx<double>* buf = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* twl = buf + lines * N3;
+  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3[i];
   __syncthreads();
-  const long long plane = (long long)h1 * N3 * N2 + h2_0;
-  const LdsAcc<T> lds{buf, 1, lines};
-  const void* usrc = d.src == 1 ? d.u64 : d.u[cur_slot(d)];
-  const GblAcc<T> src{glb(reinterpret_cast<cpx<T>*>(const_cast<void*>(usrc))) + plane, (int)zg.S, TX, 1, N2};
-  const GblAcc<T> dst{glb(reinterpret_cast<cpx<T>*>(d.spec)) + plane, (int)zg.S, TX, 1, N2};
-  fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, src, dst);
+  const LdsAcc<double> lds{buf, 1, lines};
+  const GblAcc<double> g{glb(u) + (long long)h1 * N3 * N2 + h2_0, (int)zg.S, TX, 1, N2};
+  if (INV) {
+    // in place: a single pass owns whole lines; otherwise every read precedes a barrier
+    fft_lines<double, emax<double>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, g, g);
+    return;
+  }
+  fft_lines<double, emax<double>(), false>(*plan3, lines, zg.rLines, false, twl, 1, lds, g, lds);
+  __syncthreads();
+  for (int e = threadIdx.x; e < lines * N3; e += kThreads) {
+    const int l3 = fdiv(e, zg.rLines);
+    const cpx<double> v = buf[e];
+    g.put(e - l3 * lines, l3, {v.x * scale, v.y * scale});
+  }
 }
 
 // C2R along x of u (slot 0 -> slot 3 real rows): split + first inverse pass (the
@@ -335,12 +342,13 @@ __global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) 
 // ----------------------------------------------------------------------------
 // launch wrappers
 // ----------------------------------------------------------------------------
-template <typename T>
-hipError_t launch_zexp3(const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
-                        const void* tw3T, hipStream_t s) {
-  const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
-  dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
-  hipLaunchKernelGGL(k_zexp3<T>, grid, dim3(kThreads), shm, s, descs, active, zg, plan3, (const cpx<T>*)tw3T);
+hipError_t launch_zconv3(void* u, bool inverse, const ZGeo& zg, const Plan* plan3, const void* tw3, hipStream_t s) {
+  const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<double>);
+  const dim3 grid((unsigned)(zg.H1 * zg.tiles));
+  cpx<double>* p = reinterpret_cast<cpx<double>*>(u);
+  const cpx<double>* tw = (const cpx<double>*)tw3;
+  if (inverse) hipLaunchKernelGGL(k_zconv3<true>, grid, dim3(kThreads), shm, s, p, zg, plan3, tw, 1.0);
+  else hipLaunchKernelGGL(k_zconv3<false>, grid, dim3(kThreads), shm, s, p, zg, plan3, tw, 1.0 / zg.N3);
   return hipGetLastError();
 }
 
@@ -388,8 +396,6 @@ hipError_t launch_stencil(const Desc* descs, const int* active, int nact, int ki
   return hipGetLastError();
 }
 
-template hipError_t launch_zexp3<double>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
-template hipError_t launch_zexp3<float>(const Desc*, const int*, int, const ZGeo&, const Plan*, const void*, hipStream_t);
 template hipError_t launch_xc2r<double>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template hipError_t launch_xc2r<float>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template hipError_t launch_xr2c<double>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);

@@ -13,6 +13,8 @@ namespace hz {
 // d.cmode 1: FP64 sweep of the anchor: store r in r32, no update
 // d.cmode 2: correction round: r += r32, u[1-p] = u[p] - Omega r
 // d.cmode 3: strain-based form: u[0] = Omega r (the next P1 applies it to the strains)
+// The stencil form keeps u in the mixed domain (inverse z transform of u(q)), so its
+// update subtracts the inverse z transform of Omega r (linearity of the transform).
 // ----------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void sig_dot(const cpx<T> (&s)[6], const cpx<double>* c, cpx<double>* out) {
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
       const int o = h3 * N2 + col;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if (MODE == 0 || MODE == 2) uv[i][c] = gld(uin + c * zg.S + o);
+        if (!STENCIL && (MODE == 0 || MODE == 2)) uv[i][c] = gld(uin + c * zg.S + o);
         if (MODE == 2) rv[i][c] = gld(r32in + c * zg.S + o);
       }
     }
@@ -210,19 +212,42 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
       for (int a = 0; a < 3; ++a) {
         const cpx<double> dw = {O[a][0] * r[0].x + O[a][1] * r[1].x + O[a][2] * r[2].x,
                                 O[a][0] * r[0].y + O[a][1] * r[1].y + O[a][2] * r[2].y};
-        const cpx<T> un = fr64<T>(MODE == 3 ? dw : to64(uv[i][a]) - dw);
-        gst(uout + a * zg.S + o, un);
-        // stencil form: the updated u replaces r in its LDS line (same element, same thread)
-        if (STENCIL) lds.put(a * TX + col, h3, un);
+        if (STENCIL) {
+          // Omega r replaces r in its LDS line (same element, same thread)
+          lds.put(a * TX + col, h3, fr64<T>(dw));
+        } else {
+          gst(uout + a * zg.S + o, fr64<T>(MODE == 3 ? dw : to64(uv[i][a]) - dw));
+        }
       }
     }
   }
   if (STENCIL && (MODE == 0 || MODE == 2)) {
-    // first step of the next iteration, on the lines already in LDS: the inverse z
-    // transform of the updated u into slot 0 (k_zexp3 then skips this problem)
+    // mixed-domain update: inverse z transform of Omega r on the lines in LDS, then
+    // u[1-p] = u[p] - that, element by element (loads issued CH at a time)
     __syncthreads();
-    const GblAcc<T> dst{glb(reinterpret_cast<cpx<T>*>(d.spec)) + plane, (int)zg.S, TX, 1, N2};
-    fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, lds, dst);
+    fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, lds, lds);
+    __syncthreads();
+    const int nl = lines * N3;
+#pragma unroll 1
+    for (int e0 = threadIdx.x; e0 < nl; e0 += CH * kThreads) {
+      cpx<T> v[CH];
+      int off[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int e = e0 + i * kThreads;
+        if (e >= nl) break;
+        const int l3 = fdiv(e, zg.rLines), t = e - l3 * lines;
+        const int c = fdiv(t, zg.rTX);
+        off[i] = c * (int)zg.S + l3 * N2 + (t - c * TX);
+        v[i] = gld(uin + off[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int e = e0 + i * kThreads;
+        if (e >= nl) break;
+        gst(uout + off[i], v[i] - buf[e]);
+      }
+    }
   }
   block_sum<1>(part, red);
   if (threadIdx.x == 0) d.part_res[tile] = part[0];

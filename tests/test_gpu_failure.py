@@ -76,11 +76,21 @@ def test_repeated_solves_are_bitwise_identical(scheme):
         assert np.array_equal(getattr(a, name), getattr(b, name)), name
 
 
+def _same(a, b, exact, name):
+    if exact:
+        assert np.array_equal(a, b), name
+    else:
+        scale = np.max(np.abs(b))
+        assert np.max(np.abs(a - b)) <= 1e-11 * scale, (name, np.max(np.abs(a - b)) / scale)
+
+
 @pytest.mark.parametrize("loading", [hz.HZ_LOAD_STRAIN, hz.HZ_LOAD_STRESS], ids=["strain", "stress"])
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
-def test_resume_from_checkpoint_is_bitwise(scheme, loading):
+def test_resume_from_checkpoint(scheme, loading):
     """Checkpoint = the displacement of an iterate (and its mean strain under applied
-    stress); a solve started from it continues the same iterates bit for bit."""
+    stress); a solve started from it continues the same iterates: bit for bit in the
+    Fourier form; to rounding in the stencil form, whose iterate is held as its inverse
+    z transform and converted to u(q) and back at the checkpoint."""
     shape = (16, 12, 10)
     ph, C, C0, E = random_problem(shape, 3, 62, "aniso")
     g = hz.Grid(*shape)
@@ -96,7 +106,8 @@ def test_resume_from_checkpoint_is_bitwise(scheme, loading):
     a = g.solve(E, fixed_iters=7, **kw)
     u7 = g.displacement(0)[None]
     b = g.solve(E, fixed_iters=5, trace=True, fields=True, u_init=u7, Ebar_init=a.Ebar, **kw)
-    assert np.array_equal(b.trace_residual[0, :6], full.trace_residual[0, 7:13])
-    assert np.array_equal(b.trace_mean[0, :6], full.trace_mean[0, 7:13])
+    exact = scheme == hz.HZ_SCHEME_SPECTRAL
+    _same(b.trace_residual[0, :6], full.trace_residual[0, 7:13], exact, "trace_residual")
+    _same(b.trace_mean[0, :6], full.trace_mean[0, 7:13], exact, "trace_mean")
     for name in ("mean_sigma", "Ebar", "eps", "sigma"):
-        assert np.array_equal(getattr(b, name), getattr(full, name)), name
+        _same(getattr(b, name), getattr(full, name), exact, name)
