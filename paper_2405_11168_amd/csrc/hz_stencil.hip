@@ -132,31 +132,51 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ desc
 // T1 takes the corners with an even number of -1 offsets
 __device__ __forceinline__ int tet_of(int o) { return ((o & 1) + ((o >> 1) & 1) + ((o >> 2) & 1)) & 1 ? 0 : 1; }
 
-// sigma^Tk of one voxel from the 4 corners of tetrahedron k (u4[i] = corner o_i of Tk)
+// sigma^Tk of one voxel from the 4 corners of tetrahedron k (u4[i] = corner o_i of Tk,
+// in increasing corner code).  The weights w(o) pair the corners: with
+// Tk = 1 (codes 000, 011, 101, 110): a = u1 - u0, b = u2 - u3,
+// Tk = 0 (codes 001, 010, 100, 111): a = u3 - u2, b = u0 - u1,
+// the gradient rows are 2 G_x = a + b, 2 G_y = a - b, 2 G_z = (u2 + u3) - (u0 + u1).
+// (The anisotropic variants accumulate w(o) u(o) corner by corner instead: fewer
+// live registers next to their 21 stiffness entries.)
 template <typename T, bool ISO, bool EIG, int K>
 __device__ __forceinline__ void stencil_sigma_k(const Mean<T>& Mn, const HZ_GLB T* C, int ph, cpx<T> lm,
                                                 const T (&u4)[4][3], T (&out)[6]) {
-  T G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  int i = 0;
-#pragma unroll
-  for (int o = 0; o < 8; ++o) {
-    if (tet_of(o) != K) continue;
-    const T w0 = (o & 1) ? (T)0.5 : (T)-0.5, w1 = (o & 2) ? (T)0.5 : (T)-0.5, w2 = (o & 4) ? (T)0.5 : (T)-0.5;
+  T H[3][3];  // H[a][j] = 2 du_j/dx_a
+  if constexpr (ISO) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      G[0][j] += w0 * u4[i][j];
-      G[1][j] += w1 * u4[i][j];
-      G[2][j] += w2 * u4[i][j];
+      const T a = K ? u4[1][j] - u4[0][j] : u4[3][j] - u4[2][j];
+      const T b = K ? u4[2][j] - u4[3][j] : u4[0][j] - u4[1][j];
+      H[0][j] = a + b;
+      H[1][j] = a - b;
+      H[2][j] = (u4[2][j] + u4[3][j]) - (u4[0][j] + u4[1][j]);
     }
-    ++i;
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) H[a][j] = 0;
+    int i = 0;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      if (tet_of(o) != K) continue;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        H[0][j] += (o & 1) ? u4[i][j] : -u4[i][j];
+        H[1][j] += (o & 2) ? u4[i][j] : -u4[i][j];
+        H[2][j] += (o & 4) ? u4[i][j] : -u4[i][j];
+      }
+      ++i;
+    }
   }
   T e[6];
-  e[0] = G[0][0];
-  e[1] = G[1][1];
-  e[2] = G[2][2];
-  e[3] = (T)0.5 * (G[1][2] + G[2][1]);
-  e[4] = (T)0.5 * (G[0][2] + G[2][0]);
-  e[5] = (T)0.5 * (G[0][1] + G[1][0]);
+  e[0] = (T)0.5 * H[0][0];
+  e[1] = (T)0.5 * H[1][1];
+  e[2] = (T)0.5 * H[2][2];
+  e[3] = (T)0.25 * (H[1][2] + H[2][1]);
+  e[4] = (T)0.25 * (H[0][2] + H[2][0]);
+  e[5] = (T)0.25 * (H[0][1] + H[1][0]);
   if (ISO) constitutive_iso<EIG, T>(lm.x, lm.y, Mn, ph, e, out);
   else constitutive<EIG, T>(C + ph * 24, Mn, ph, e, out);
 }
@@ -297,17 +317,19 @@ __global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) 
       }
       __syncthreads();
       if (own) {
-        // corner (cx, cy) receives sigma^Tk of voxel (cx - o1, cy - o2) for o in Tk
+        // corner (cx, cy) receives sigma^Tk of voxel (cx - o1, cy - o2) for o in Tk;
+        // with w(o) = +-1/2 the sums carry 2 sigma.w and the 1/2 is applied at the store
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
           if (tet_of(o) != k) continue;
           const int vx = cx + ((o & 1) ? 0 : 1), vy = cy + ((o & 2) ? 0 : 1);
-          const T w0 = (o & 1) ? (T)0.5 : (T)-0.5, w1 = (o & 2) ? (T)0.5 : (T)-0.5, w2 = (o & 4) ? (T)0.5 : (T)-0.5;
+          auto pm = [](bool plus, T x) { return plus ? x : -x; };
+          const bool p0 = o & 1, p1 = o & 2, p2 = o & 4;
           const T s0 = sb[0][vy][vx], s1 = sb[1][vy][vx], s2 = sb[2][vy][vx];
           const T s3 = sb[3][vy][vx], s4 = sb[4][vy][vx], s5 = sb[5][vy][vx];
-          const T f0 = s0 * w0 + s5 * w1 + s4 * w2;
-          const T f1 = s5 * w0 + s1 * w1 + s3 * w2;
-          const T f2 = s4 * w0 + s3 * w1 + s2 * w2;
+          const T f0 = pm(p0, s0) + pm(p1, s5) + pm(p2, s4);
+          const T f1 = pm(p0, s5) + pm(p1, s1) + pm(p2, s3);
+          const T f2 = pm(p0, s4) + pm(p1, s3) + pm(p2, s2);
           if (o & 4) {
             g0[0] += f0; g0[1] += f1; g0[2] += f2;
           } else {
@@ -320,7 +342,7 @@ __global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) 
       if (p > z0) {
         const int at = (p - 1) * NP + (y0 + cy) * N1 + (x0 + cx);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) gr[(long long)j * Nn + at] = acc[j] + g1[j];
+        for (int j = 0; j < 3; ++j) gr[(long long)j * Nn + at] = (T)0.5 * (acc[j] + g1[j]);
       }
 #pragma unroll
       for (int j = 0; j < 3; ++j) acc[j] = g0[j];
