@@ -187,6 +187,23 @@ def test_fp32_refine_ceff_within_1e6_of_converged_oracle(scheme):
 
 
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_fp32_refine_displacement_matches_converged_oracle(scheme):
+    """The displacement an FP32+refine solve reports is its FP64 anchor U as u(q) (the
+    stencil form holds U as its inverse z transform while it iterates)."""
+    p = syn.sphere16()
+    g = hz.Grid(*p.shape)
+    g.set_material(p.C, p.phase)
+    r = g.solve(p.loads[:1], tol=1e-9, C0=p.C0, precision=hz.HZ_FP32_REFINE, scheme=scheme)
+    assert r.status[0] == hz.HZ_OK
+    u = g.displacement(0)
+    ref = tetra.basic_scheme(p.phase, p.C, p.C0, p.loads[0], tol=1e-12, keep_fields=False)
+    uo = oracle_u_in_library_layout(ref.u_hat, p.shape)
+    eu = np.abs(u - uo).max() / np.abs(uo).max()
+    _say(f"  refine displacement rel err {eu:.2e} (residual {r.residual[0]:.2e})")
+    assert eu < 1e-6
+
+
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
 def test_large_non_power_of_two_cell_first_iterates(scheme):
     """The 192 x 192 x 320 cell (11.8 M voxels, radix 3 and 5 passes, narrow z tiles),
     Boolean spheres to 25% with contrast 1e2: iterates 0..1 against the oracle."""
