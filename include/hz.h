@@ -116,7 +116,11 @@ typedef struct {
   const double* u_init;     /* optional [n_loads][3][n1/2+1][n3][n2] complex (re,im) FP64 in the
                                layout and phase convention of hz_get_displacement: iterate 0 is
                                this displacement instead of 0 (resume from a checkpoint).  HZ_FP64,
-                               spectral or stencil scheme, hz_solve only; NULL: start from 0    */
+                               spectral or stencil scheme, hz_solve only; NULL: start from 0.
+                               The resumed iterates equal those of an uninterrupted solve bit for
+                               bit in the spectral scheme and to rounding in the stencil scheme,
+                               which holds the displacement as its inverse z transform while it
+                               iterates                                                         */
   const double* Ebar_init;  /* optional [n_loads][6]: under HZ_LOAD_STRESS, the mean strain of
                                iterate 0 (hz_info.Ebar of the checkpoint); NULL: lambda0^-1:sigma^a */
 } hz_opts;
