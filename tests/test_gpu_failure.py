@@ -111,3 +111,25 @@ def test_resume_from_checkpoint(scheme, loading):
     _same(b.trace_mean[0, :6], full.trace_mean[0, 7:13], exact, "trace_mean")
     for name in ("mean_sigma", "Ebar", "eps", "sigma"):
         _same(getattr(b, name), getattr(full, name), exact, name)
+
+
+@pytest.mark.parametrize("shape", [(16, 8, 16), (8, 6, 4)], ids=["z16", "z4"])
+def test_stencil_resume_with_single_pass_z_transforms(shape):
+    """N3 = 16 and 4 are single radix passes, where the start-of-solve conversion of the
+    given displacement runs in place with each thread owning whole z lines; two solves
+    of 4 + 5 iterations continue the 9-iteration solve to rounding."""
+    ph, C, C0, E = random_problem(shape, 2, 63, "iso")
+    g = hz.Grid(*shape)
+    g.set_material(C, ph)
+    if not g.scheme_available(hz.HZ_SCHEME_STENCIL):
+        pytest.skip(f"stencil form not available for {shape}")
+    kw = dict(C0=C0, scheme=hz.HZ_SCHEME_STENCIL)
+    full = g.solve(E, fixed_iters=9, trace=True, fields=True, **kw)
+    u9 = g.displacement(0)
+    g.solve(E, fixed_iters=4, **kw)
+    u4 = g.displacement(0)[None]
+    b = g.solve(E, fixed_iters=5, trace=True, fields=True, u_init=u4, **kw)
+    _same(b.trace_residual[0, :6], full.trace_residual[0, 4:10], False, "trace_residual")
+    for name in ("mean_sigma", "eps", "sigma"):
+        _same(getattr(b, name), getattr(full, name), False, name)
+    _same(g.displacement(0), u9, False, "u")
