@@ -161,6 +161,46 @@ __device__ __forceinline__ void constitutive(const HZ_GLB T* __restrict__ Cp, co
   eigenstress<EIG>(M, ph, s);
 }
 
+// the same law for the two tetrahedra of one voxel (one phase): the stiffness entries
+// are loaded once for both
+template <bool EIG, typename T>
+__device__ __forceinline__ void constitutive_pair(const HZ_GLB T* __restrict__ Cp, const Mean<T>& M, int ph,
+                                                  const T (&de0)[6], const T (&de1)[6], T (&s0)[6], T (&s1)[6]) {
+  T g0[6], g1[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    g0[c] = M.Eb[c] + de0[c];
+    g1[c] = M.Eb[c] + de1[c];
+  }
+#pragma unroll
+  for (int c = 3; c < 6; ++c) {  // engineering shears
+    g0[c] *= (T)2;
+    g1[c] *= (T)2;
+  }
+  T Cu[24];
+#pragma unroll
+  for (int i = 0; i < 24; i += 2) {
+    const cpx<T> v = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(Cp) + i / 2);
+    Cu[i] = v.x;
+    Cu[i + 1] = v.y;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T a0 = 0, a1 = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int a = i < j ? i : j, b = i < j ? j : i;
+      const T cij = Cu[a * 6 - a * (a - 1) / 2 + (b - a)];
+      a0 += cij * g0[j];
+      a1 += cij * g1[j];
+    }
+    s0[i] = a0;
+    s1[i] = a1;
+  }
+  eigenstress<EIG>(M, ph, s0);
+  eigenstress<EIG>(M, ph, s1);
+}
+
 // isotropic phase: sigma = lambda tr(eps) I + 2 mu eps - lambda:eps0
 template <bool EIG, typename T>
 __device__ __forceinline__ void constitutive_iso(T lam, T mu, const Mean<T>& M, int ph, const T (&de)[6],

@@ -1,5 +1,7 @@
 // HIP kernels (gfx950) of the stencil form of the iteration: 3-field z and x
 // transforms around the real-space strain / constitutive / corner-force kernel.
+#include <type_traits>
+
 #include "hz_device.h"
 
 namespace hz {
@@ -132,53 +134,37 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ desc
 // T1 takes the corners with an even number of -1 offsets
 __device__ __forceinline__ int tet_of(int o) { return ((o & 1) + ((o >> 1) & 1) + ((o >> 2) & 1)) & 1 ? 0 : 1; }
 
-// sigma^Tk of one voxel from the 4 corners of tetrahedron k (u4[i] = corner o_i of Tk,
+// strain of tetrahedron k of one voxel from its 4 corners (u4[i] = corner o_i of Tk,
 // in increasing corner code).  The weights w(o) pair the corners: with
 // Tk = 1 (codes 000, 011, 101, 110): a = u1 - u0, b = u2 - u3,
 // Tk = 0 (codes 001, 010, 100, 111): a = u3 - u2, b = u0 - u1,
 // the gradient rows are 2 G_x = a + b, 2 G_y = a - b, 2 G_z = (u2 + u3) - (u0 + u1).
-// (The anisotropic variants accumulate w(o) u(o) corner by corner instead: fewer
-// live registers next to their 21 stiffness entries.)
-template <typename T, bool ISO, bool EIG, int K>
-__device__ __forceinline__ void stencil_sigma_k(const Mean<T>& Mn, const HZ_GLB T* C, int ph, cpx<T> lm,
-                                                const T (&u4)[4][3], T (&out)[6]) {
+template <typename T, int K>
+__device__ __forceinline__ void stencil_strain_k(const T (&u4)[4][3], T (&e)[6]) {
   T H[3][3];  // H[a][j] = 2 du_j/dx_a
-  if constexpr (ISO) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const T a = K ? u4[1][j] - u4[0][j] : u4[3][j] - u4[2][j];
-      const T b = K ? u4[2][j] - u4[3][j] : u4[0][j] - u4[1][j];
-      H[0][j] = a + b;
-      H[1][j] = a - b;
-      H[2][j] = (u4[2][j] + u4[3][j]) - (u4[0][j] + u4[1][j]);
-    }
-  } else {
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) H[a][j] = 0;
-    int i = 0;
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      if (tet_of(o) != K) continue;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        H[0][j] += (o & 1) ? u4[i][j] : -u4[i][j];
-        H[1][j] += (o & 2) ? u4[i][j] : -u4[i][j];
-        H[2][j] += (o & 4) ? u4[i][j] : -u4[i][j];
-      }
-      ++i;
-    }
+  for (int j = 0; j < 3; ++j) {
+    const T a = K ? u4[1][j] - u4[0][j] : u4[3][j] - u4[2][j];
+    const T b = K ? u4[2][j] - u4[3][j] : u4[0][j] - u4[1][j];
+    H[0][j] = a + b;
+    H[1][j] = a - b;
+    H[2][j] = (u4[2][j] + u4[3][j]) - (u4[0][j] + u4[1][j]);
   }
-  T e[6];
   e[0] = (T)0.5 * H[0][0];
   e[1] = (T)0.5 * H[1][1];
   e[2] = (T)0.5 * H[2][2];
   e[3] = (T)0.25 * (H[1][2] + H[2][1]);
   e[4] = (T)0.25 * (H[0][2] + H[2][0]);
   e[5] = (T)0.25 * (H[0][1] + H[1][0]);
-  if (ISO) constitutive_iso<EIG, T>(lm.x, lm.y, Mn, ph, e, out);
-  else constitutive<EIG, T>(C + ph * 24, Mn, ph, e, out);
+}
+
+// sigma^Tk of one voxel of an isotropic phase
+template <typename T, bool EIG, int K>
+__device__ __forceinline__ void stencil_sigma_iso_k(const Mean<T>& Mn, int ph, cpx<T> lm, const T (&u4)[4][3],
+                                                    T (&out)[6]) {
+  T e[6];
+  stencil_strain_k<T, K>(u4, e);
+  constitutive_iso<EIG, T>(lm.x, lm.y, Mn, ph, e, out);
 }
 
 // Strain, constitutive law and corner force in real space.  A block owns a
@@ -188,18 +174,22 @@ __device__ __forceinline__ void stencil_sigma_k(const Mean<T>& Mn, const HZ_GLB 
 // and the corners gather it, which completes the force of corner plane p-1 and
 // starts that of corner plane p.  Corner plane p+1
 // is fetched into registers one step ahead, so its latency overlaps the work.
-// Occupancy: one tetrahedron's stresses in LDS at a time (35 KB per block in FP64)
-// lets 4 blocks share a CU; the register bounds below are the largest that compile
-// without spills (FP64: 4 waves per SIMD without eigenstrains, 3 with; FP32: 5 for
-// the isotropic variant without eigenstrains).
+// Occupancy: isotropic phases keep one tetrahedron's stresses in LDS at a time (35 KB
+// per block in FP64), which lets 4 blocks share a CU.  The anisotropic variants, held
+// to 3 waves per SIMD by their registers anyway, compute both tetrahedra of a voxel
+// in one stage (50 KB): the 21 stiffness entries are loaded once per voxel and a
+// z step has 2 barriers instead of 4.  The register bounds below are the largest that
+// compile without spills (FP64: 4 waves per SIMD for isotropic phases without
+// eigenstrains, 3 otherwise; FP32: 5 for the isotropic variant without eigenstrains).
 template <typename T, bool ISO, bool EIG>
 __global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T) == 8 ? 3 : 1)) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
                                                       SGeo sg) {
   constexpr int UX = kStX + 2, UY = kStY + 2, VX = kStX + 1, VY = kStY + 1;
   constexpr int UP = 3 * UY * UX;                      // corner values per plane
   constexpr int NL = (UP + kThreads - 1) / kThreads;   // per thread
+  constexpr bool PAIR = !ISO;                          // both tetrahedra per stage
   __shared__ T ub[2][UP];                              // [slot][c][yy][xx]
-  __shared__ T sb[6][VY][VX];  // sigma of one tetrahedron at a time
+  __shared__ T sb[PAIR ? 2 : 1][6][VY][VX];            // sigma of one (or both) tetrahedra
   __shared__ double red[6 * 4];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d) || (d.iso != 0) != ISO || (d.tau64 != nullptr) != EIG) return;
@@ -286,15 +276,10 @@ __global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) 
   for (int p = z0; p <= z0 + wz; ++p) {
     const int cur = p & 1, prv = cur ^ 1;
     T g1[3] = {0, 0, 0}, g0[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      __syncthreads();  // k = 0: plane p stashed; k = 1: the gather of tetrahedron 0 is done with sb
-      // sigma^Tk of voxel plane p over (wx+1) x (wy+1) voxels
-#pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-        if (tid + sl * kThreads >= nv) continue;
-        const int vy = vys[sl], vx = vxs[sl];
-        T u4[4][3];
+    if constexpr (PAIR) {
+      // the 4 corners of tetrahedron k of voxel (vx, vy) of plane p
+      auto corners = [&](auto kc, int vx, int vy, T (&u4)[4][3]) {
+        constexpr int k = decltype(kc)::value;
         int i = 0;
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
@@ -305,28 +290,19 @@ __global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) 
           for (int j = 0; j < 3; ++j) u4[i][j] = ub[slot][(j * UY + iy) * UX + ix];
           ++i;
         }
-        T out[6];
-        if (k == 0) stencil_sigma_k<T, ISO, EIG, 0>(Mn, C, cph[sl], clm[sl], u4, out);
-        else stencil_sigma_k<T, ISO, EIG, 1>(Mn, C, cph[sl], clm[sl], u4, out);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) sb[c][vy][vx] = out[c];
-        if (vx < wx && vy < wy && p < z0 + wz) {
-#pragma unroll
-          for (int c = 0; c < 6; ++c) sacc[c] += 0.5 * (double)out[c];
-        }
-      }
-      __syncthreads();
-      if (own) {
-        // corner (cx, cy) receives sigma^Tk of voxel (cx - o1, cy - o2) for o in Tk;
-        // with w(o) = +-1/2 the sums carry 2 sigma.w and the 1/2 is applied at the store
+      };
+      // corner (cx, cy) receives sigma^Tk of voxel (cx - o1, cy - o2) for o in Tk;
+      // with w(o) = +-1/2 the sums carry 2 sigma.w and the 1/2 is applied at the store
+      auto gather = [&](auto kc, const T (&sk)[6][VY][VX]) {
+        constexpr int k = decltype(kc)::value;
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
           if (tet_of(o) != k) continue;
           const int vx = cx + ((o & 1) ? 0 : 1), vy = cy + ((o & 2) ? 0 : 1);
           auto pm = [](bool plus, T x) { return plus ? x : -x; };
           const bool p0 = o & 1, p1 = o & 2, p2 = o & 4;
-          const T s0 = sb[0][vy][vx], s1 = sb[1][vy][vx], s2 = sb[2][vy][vx];
-          const T s3 = sb[3][vy][vx], s4 = sb[4][vy][vx], s5 = sb[5][vy][vx];
+          const T s0 = sk[0][vy][vx], s1 = sk[1][vy][vx], s2 = sk[2][vy][vx];
+          const T s3 = sk[3][vy][vx], s4 = sk[4][vy][vx], s5 = sk[5][vy][vx];
           const T f0 = pm(p0, s0) + pm(p1, s5) + pm(p2, s4);
           const T f1 = pm(p0, s5) + pm(p1, s1) + pm(p2, s3);
           const T f2 = pm(p0, s4) + pm(p1, s3) + pm(p2, s2);
@@ -334,6 +310,94 @@ __global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) 
             g0[0] += f0; g0[1] += f1; g0[2] += f2;
           } else {
             g1[0] += f0; g1[1] += f1; g1[2] += f2;
+          }
+        }
+      };
+      using K0 = std::integral_constant<int, 0>;
+      using K1 = std::integral_constant<int, 1>;
+      __syncthreads();  // plane p stashed, the previous gather done with sb
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        if (tid + sl * kThreads >= nv) continue;
+        const int vy = vys[sl], vx = vxs[sl];
+        T e0[6], e1[6];
+        {
+          T u4[4][3];
+          corners(K0{}, vx, vy, u4);
+          stencil_strain_k<T, 0>(u4, e0);
+        }
+        {
+          T u4[4][3];
+          corners(K1{}, vx, vy, u4);
+          stencil_strain_k<T, 1>(u4, e1);
+        }
+        T s0[6], s1[6];
+        constitutive_pair<EIG, T>(C + cph[sl] * 24, Mn, cph[sl], e0, e1, s0, s1);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          sb[0][c][vy][vx] = s0[c];
+          sb[PAIR ? 1 : 0][c][vy][vx] = s1[c];
+        }
+        if (vx < wx && vy < wy && p < z0 + wz) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sacc[c] += 0.5 * ((double)s0[c] + (double)s1[c]);
+        }
+      }
+      __syncthreads();
+      if (own) {
+        gather(K0{}, sb[0]);
+        gather(K1{}, sb[PAIR ? 1 : 0]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        __syncthreads();  // k = 0: plane p stashed; k = 1: the gather of tetrahedron 0 is done with sb
+        // sigma^Tk of voxel plane p over (wx+1) x (wy+1) voxels
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          if (tid + sl * kThreads >= nv) continue;
+          const int vy = vys[sl], vx = vxs[sl];
+          T u4[4][3];
+          int i = 0;
+#pragma unroll
+          for (int o = 0; o < 8; ++o) {
+            if (tet_of(o) != k) continue;
+            const int ix = vx + ((o & 1) ? 1 : 0), iy = vy + ((o & 2) ? 1 : 0);
+            const int slot = (o & 4) ? cur : prv;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) u4[i][j] = ub[slot][(j * UY + iy) * UX + ix];
+            ++i;
+          }
+          T out[6];
+          if (k == 0) stencil_sigma_iso_k<T, EIG, 0>(Mn, cph[sl], clm[sl], u4, out);
+          else stencil_sigma_iso_k<T, EIG, 1>(Mn, cph[sl], clm[sl], u4, out);
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sb[0][c][vy][vx] = out[c];
+          if (vx < wx && vy < wy && p < z0 + wz) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sacc[c] += 0.5 * (double)out[c];
+          }
+        }
+        __syncthreads();
+        if (own) {
+          // corner (cx, cy) receives sigma^Tk of voxel (cx - o1, cy - o2) for o in Tk;
+          // with w(o) = +-1/2 the sums carry 2 sigma.w and the 1/2 is applied at the store
+#pragma unroll
+          for (int o = 0; o < 8; ++o) {
+            if (tet_of(o) != k) continue;
+            const int vx = cx + ((o & 1) ? 0 : 1), vy = cy + ((o & 2) ? 0 : 1);
+            auto pm = [](bool plus, T x) { return plus ? x : -x; };
+            const bool p0 = o & 1, p1 = o & 2, p2 = o & 4;
+            const T s0 = sb[0][0][vy][vx], s1 = sb[0][1][vy][vx], s2 = sb[0][2][vy][vx];
+            const T s3 = sb[0][3][vy][vx], s4 = sb[0][4][vy][vx], s5 = sb[0][5][vy][vx];
+            const T f0 = pm(p0, s0) + pm(p1, s5) + pm(p2, s4);
+            const T f1 = pm(p0, s5) + pm(p1, s1) + pm(p2, s3);
+            const T f2 = pm(p0, s4) + pm(p1, s3) + pm(p2, s2);
+            if (o & 4) {
+              g0[0] += f0; g0[1] += f1; g0[2] += f2;
+            } else {
+              g1[0] += f0; g1[1] += f1; g1[2] += f2;
+            }
           }
         }
       }
