@@ -14,7 +14,10 @@ through the transforms) is timed beside it for context.
 Prints ONE JSON line:
   value          voxel-iterations/s (128^3 voxels x 6 loads x steps / timed seconds)
   roofline       the dominant kernel's algorithmic bytes per launch / its mean
-                 HIP-event duration, against 8 TB/s
+                 HIP-event duration over the timed iterations (events around that
+                 kernel's launches only), against 8 TB/s
+  per_kernel     mean launch durations from an untimed run with events around every
+                 launch (it also picks the dominant kernel)
   cpu_baseline   the CPU oracle timed on the host on a bounded sample
   time_to_1e-6   FP32+refinement vs plain FP64 device time to an FP64-verified
                  residual of 1e-6 on the 256^3 Voronoi polycrystal (6 loads)
@@ -298,19 +301,25 @@ def main():
     # warmup, then exactly `steps` iterations of all six loads
     if a.warmup > 0:
         g.solve(p.loads, C0=p.C0, fixed_iters=a.warmup - 1, check_every=1 << 20, scheme=sch)
-    # the timed region carries HIP events around every launch on the library's stream:
-    # they give the per-kernel durations of exactly the iterations timed (and cost the
-    # value a few percent: a run without them is ~3% faster)
-    torch.cuda.synchronize()
+    # per-kernel breakdown (untimed): HIP events around every launch of a short run
     g.profile(True)
+    g.solve(p.loads, C0=p.C0, fixed_iters=max(4, a.steps // 4) - 1, check_every=1 << 20, scheme=sch)
+    torch.cuda.synchronize()
+    g.profile(False)
+    prof = g.profile_read()
+    dom_name = max(prof, key=lambda k: prof[k][0])
+    # the timed region carries HIP events around every launch of the dominant kernel on
+    # the library's stream: its roofline comes from exactly the iterations timed
+    torch.cuda.synchronize()
+    g.profile(True, only=dom_name)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = g.solve(p.loads, C0=p.C0, fixed_iters=a.steps - 1, check_every=1 << 20, scheme=sch)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     g.profile(False)
-    prof = g.profile_read()
-    assert np.all(r.iters == a.steps - 1)
+    timed = g.profile_read()
+    assert np.all(r.iters == a.steps - 1) and set(timed) == {dom_name}
     value = N * 6 * a.steps / dt
     log(f"bench: {a.steps} steps in {dt * 1e3:.1f} ms -> {value / 1e9:.3f} G voxel-iters/s")
     # the other realisation, same workload, for context (not the headline value)
@@ -327,13 +336,14 @@ def main():
                "voxel_iters_per_s": N * 6 * k2 / (time.perf_counter() - t1)}
         log(f"bench: other scheme {alt}")
 
-    # roofline of the dominant kernel from the library's HIP events on its stream
+    # roofline of the dominant kernel from the library's HIP events on its stream, over
+    # the timed iterations
     kinds = {}
     for name, (ms, cnt) in prof.items():
         kind, prec = name.rsplit("_", 1)
         kinds[name] = (kind, prec, ms, cnt)
-    dom = max(kinds.values(), key=lambda t: t[2])
-    kind, prec, ms, cnt = dom
+    kind, prec = dom_name.rsplit("_", 1)
+    ms, cnt = timed[dom_name]
     per_launch_bytes = kernel_bytes(kind, S, N, 6, 16 if prec == "f64" else 8)
     avg_s = ms / cnt / 1e3
     achieved = per_launch_bytes / avg_s / 1e9

@@ -206,9 +206,11 @@ int hz_scheme_available(hz_grid g, int32_t scheme);
 int hz_reference_medium(int32_t n_phases, const double* C_voigt, double C0_out[36]);
 
 /* Per-kernel device timing with HIP events on the bound stream.
- * hz_profile(g, 1) starts recording (and clears totals), hz_profile(g, 0) stops.
- * hz_profile_read fills up to max entries: name (static string), total ms, launches;
- * returns the number of kernel kinds. */
+ * hz_profile(g, 1) starts recording every launch (and clears totals); hz_profile(g, 2 + i)
+ * records only the launches of entry i of hz_profile_read (one kernel kind and precision,
+ * so the other launches carry no events); hz_profile(g, 0) stops.  HZ_EINVAL for other
+ * values.  hz_profile_read fills up to max entries: name (static string), total ms,
+ * launches; returns the number of entries (kernel kinds x 2 precisions). */
 int hz_profile(hz_grid g, int32_t enable);
 int hz_profile_read(hz_grid g, int32_t max, const char** names, double* total_ms, int64_t* launches);
 

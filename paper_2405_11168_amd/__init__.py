@@ -220,8 +220,19 @@ class Grid:
         return out[..., 0] + 1j * out[..., 1]
 
     # -- profiling ---------------------------------------------------------------
-    def profile(self, enable=True):
-        check(lib().hz_profile(self._h, 1 if enable else 0))
+    def profile(self, enable=True, only=None):
+        """Start (enable) or stop per-kernel event timing; `only` names one entry of
+        profile_read (e.g. "stencil_f64") to time that kernel's launches alone."""
+        mode = 1 if enable else 0
+        if enable and only is not None:
+            n = 64
+            names = (ctypes.c_char_p * n)()
+            k = check(lib().hz_profile_read(self._h, n, names, None, None))
+            idx = [names[i].decode() for i in range(min(k, n))]
+            if only not in idx:
+                raise ValueError(f"unknown kernel entry {only!r}")
+            mode = 2 + idx.index(only)
+        check(lib().hz_profile(self._h, mode))
 
     def profile_read(self):
         n = 64

@@ -602,8 +602,10 @@ int hz_reference_medium(int32_t n_phases, const double* C_voigt, double C0_out[3
 int hz_profile(hz_grid g, int32_t enable) {
   HZ_GUARD_BEGIN
   if (!g) fail(HZ_EINVAL, "NULL handle");
+  if (enable < 0 || enable >= 2 + 2 * K_COUNT) fail(HZ_EINVAL, "profile mode out of range");
   if (enable) g->prof.reset();
   g->prof.on = enable != 0;
+  g->prof.only = enable >= 2 ? enable - 2 : -1;
   return HZ_OK;
   HZ_GUARD_END
 }

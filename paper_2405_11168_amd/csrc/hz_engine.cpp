@@ -594,14 +594,14 @@ struct Launch {
     return p.pool[p.used++];
   }
   Launch(Engine& eng, int kind, int dbl) : e(eng), key(kind * 2 + dbl) {
-    if (e.prof->on) {
+    if (e.prof->records(key)) {
       a = take();
       hip_check(hipEventRecord(a, e.stream), "hipEventRecord");
     }
   }
   void done(hipError_t err, const char* what) {
     hip_check(err, what);
-    if (e.prof->on) {
+    if (e.prof->records(key)) {
       hipEvent_t b = take();
       hip_check(hipEventRecord(b, e.stream), "hipEventRecord");
       e.prof->pending.push_back({key, {a, b}});

@@ -160,6 +160,8 @@ extern const char* const kKindNames[K_COUNT];
 
 struct Prof {
   bool on = false;
+  int only = -1;  // >= 0: record only launches with this key (kind * 2 + FP64)
+  bool records(int key) const { return on && (only < 0 || only == key); }
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
   std::vector<hipEvent_t> pool;
   size_t used = 0;

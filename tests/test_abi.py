@@ -166,3 +166,20 @@ def test_eigenstrain_and_loading_validation():
     o = hz._opts()
     assert lib.hz_effective_stiffness(g._h, ctypes.byref(o), Ce.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                       None) == _abi.HZ_EINVAL
+
+
+def test_profile_modes():
+    """hz_profile: 0 off, 1 every launch, 2 + i one entry of hz_profile_read; other
+    values are rejected (host-side state only, no device needed)."""
+    lib = _abi.load()
+    g = hz.Grid(8, 8, 8)
+    n = lib.hz_profile_read(g._h, 0, None, None, None)
+    assert n > 0 and n % 2 == 0
+    for mode in (1, 0, 2, 2 + n - 1, 0):
+        assert lib.hz_profile(g._h, mode) == _abi.HZ_OK, mode
+    for mode in (-1, 2 + n):
+        assert lib.hz_profile(g._h, mode) == _abi.HZ_EINVAL, mode
+    g.profile(True, only="stencil_f64")
+    g.profile(False)
+    with pytest.raises(ValueError):
+        g.profile(True, only="no_such_kernel_f64")
