@@ -223,17 +223,19 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
   }
   if (STENCIL && (MODE == 0 || MODE == 2)) {
     // mixed-domain update: inverse z transform of Omega r on the lines in LDS, then
-    // u[1-p] = u[p] - that, element by element (loads issued CH at a time)
+    // u[1-p] = u[p] - that, element by element (loads issued CT at a time: the
+    // transform's registers are free by then)
     __syncthreads();
     fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, lds, lds);
     __syncthreads();
     const int nl = lines * N3;
+    constexpr int CT = 12;
 #pragma unroll 1
-    for (int e0 = threadIdx.x; e0 < nl; e0 += CH * kThreads) {
-      cpx<T> v[CH];
-      int off[CH];
+    for (int e0 = threadIdx.x; e0 < nl; e0 += CT * kThreads) {
+      cpx<T> v[CT];
+      int off[CT];
 #pragma unroll
-      for (int i = 0; i < CH; ++i) {
+      for (int i = 0; i < CT; ++i) {
         const int e = e0 + i * kThreads;
         if (e >= nl) break;
         const int l3 = fdiv(e, zg.rLines), t = e - l3 * lines;
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
         v[i] = gld(uin + off[i]);
       }
 #pragma unroll
-      for (int i = 0; i < CH; ++i) {
+      for (int i = 0; i < CT; ++i) {
         const int e = e0 + i * kThreads;
         if (e >= nl) break;
         gst(uout + off[i], v[i] - buf[e]);
