@@ -389,32 +389,18 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
 }
 
 // U64 += delta (refinement), delta in FP32
-// kAccU elements per thread, all loads in flight together (the anchor's loads do not
-// wait for the parity read)
-constexpr int kAccU = 4;
 __global__ __launch_bounds__(kThreads) void k_accumulate(const Desc* __restrict__ descs,
                                                          const int* __restrict__ active,
                                                          long long n3c) {
   const Desc& d = descs[active[blockIdx.y]];
-  const long long i0 = (long long)blockIdx.x * (kAccU * kThreads) + threadIdx.x;
-  cpx<double> b[kAccU];
-#pragma unroll
-  for (int u = 0; u < kAccU; ++u) {
-    const long long idx = i0 + u * kThreads;
-    if (idx < n3c) b[u] = ld<double>(d.u64, idx);
-  }
+  const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= n3c) return;
   const int p = (int)d.status[ST_PARITY];
-  cpx<float> a[kAccU];
-#pragma unroll
-  for (int u = 0; u < kAccU; ++u) {
-    const long long idx = i0 + u * kThreads;
-    if (idx < n3c) a[u] = ld<float>(d.u[p], idx);
-  }
-#pragma unroll
-  for (int u = 0; u < kAccU; ++u) {
-    const long long idx = i0 + u * kThreads;
-    if (idx < n3c) st<double>(d.u64, idx, cpx<double>{b[u].x + (double)a[u].x, b[u].y + (double)a[u].y});
-  }
+  const cpx<float> a = ld<float>(d.u[p], idx);
+  cpx<double> b = ld<double>(d.u64, idx);
+  b.x += (double)a.x;
+  b.y += (double)a.y;
+  st<double>(d.u64, idx, b);
 }
 
 // zero-fill (used instead of memset so every clear is an ordinary kernel)
@@ -463,7 +449,7 @@ hipError_t launch_finalize(const Desc* descs, const int* active, int nact, const
 
 hipError_t launch_accumulate(const Desc* descs, const int* active, int nact, long long n3c,
                              hipStream_t s) {
-  dim3 grid((unsigned)((n3c + kAccU * kThreads - 1) / (kAccU * kThreads)), nact);
+  dim3 grid((unsigned)((n3c + kThreads - 1) / kThreads), nact);
   hipLaunchKernelGGL(k_accumulate, grid, dim3(kThreads), 0, s, descs, active, n3c);
   return hipGetLastError();
 }
