@@ -220,3 +220,33 @@ def test_large_non_power_of_two_cell_first_iterates(scheme):
     em = np.abs(r.trace_mean[0, : K + 1] - ref.mean_history).max() / np.abs(ref.mean_history).max()
     _say(f"  192x192x320: residual hist {eh:.2e} <sigma> {em:.2e}")
     assert eh < 1e-10 and em < 1e-12
+
+
+def _full_size_iterates_both_forms(p, E, K, label):
+    """Iterates 0..K of one load in both forms against one oracle run."""
+    g = hz.Grid(*p.shape)
+    g.set_material(p.C, p.phase)
+    _say(f"  {label}: oracle, {K} iteration(s) of {np.prod(p.shape)} voxels")
+    ref = tetra.basic_scheme(p.phase, p.C, p.C0, E[0], fixed_iters=K, keep_fields=False)
+    for scheme in SCHEMES:
+        if not g.scheme_available(scheme):
+            continue
+        r = g.solve(E, C0=p.C0, fixed_iters=K, trace=True, scheme=scheme)
+        eh = np.max(np.abs(r.trace_residual[0, : K + 1] - ref.history) / ref.history)
+        em = np.abs(r.trace_mean[0, : K + 1] - ref.mean_history).max() / np.abs(ref.mean_history).max()
+        _say(f"  {label} scheme {scheme}: residual hist {eh:.2e} <sigma> {em:.2e}")
+        assert eh < 1e-10 and em < 1e-12
+
+
+def test_voronoi256_polycrystal_first_iterates():
+    """The 256^3 Voronoi polycrystal (200 rotated cubic grains: every phase anisotropic,
+    the time-to-1e-6 benchmark cell), a shear load: iterates 0..1 against the oracle."""
+    p = syn.polycrystal()
+    _full_size_iterates_both_forms(p, p.loads[3:4], 1, "voronoi256")
+
+
+def test_spheres256_voids_first_iterates():
+    """256^3 Boolean spheres to 25% as voids (zero stiffness), the infinite-contrast cell:
+    iterates 0..1 against the oracle."""
+    p = syn.sphere_contrast((256, 256, 256), 0.0)
+    _full_size_iterates_both_forms(p, p.loads, 1, "spheres256 voids")
