@@ -52,8 +52,9 @@ extern "C" {
 
 #define HZ_OK 0
 #define HZ_NOT_CONVERGED 1   /* max_iters reached; outputs written from the last iterate  */
-#define HZ_STAGNATED 2       /* refinement: 3 FP64 sweeps in a row gained < 10% (a rounding
-                                floor above tol); U of the last sweep is reported         */
+#define HZ_STAGNATED 2       /* reserved: a refinement that stops gaining (3 FP64 sweeps in
+                                a row under 10%, or a correction that diverges) continues
+                                as plain FP64 iterations from U (hz_info.precision_used)  */
 #define HZ_PENDING 3         /* hz_server_query: the request has not finished yet          */
 #define HZ_EINVAL (-1)       /* NULL pointer, size <= 0, unsupported size or option        */
 #define HZ_EODD (-2)         /* a grid dimension is odd (the scheme needs even N_i)        */
@@ -129,7 +130,8 @@ typedef struct {
   int32_t status;           /* HZ_OK, HZ_NOT_CONVERGED, HZ_STAGNATED or HZ_EDIVERGED           */
   int32_t iters;            /* updates applied to the reported iterate                          */
   int32_t outer_rounds;     /* FP64 sweeps (refinement); 0 for HZ_FP64                          */
-  int32_t precision_used;   /* HZ_FP64 or HZ_FP32_REFINE                                        */
+  int32_t precision_used;   /* HZ_FP32_REFINE, or HZ_FP64: an FP64 solve, or a refinement that
+                               fell back to FP64 iterations for the rest of its budget          */
   double residual;          /* eps of the reported iterate, measured in FP64                    */
   double seconds;           /* device time from solve start to the reported iterate            */
   double seconds_to_1e6;    /* device time to the first FP64-verified eps < 1e-6, or -1         */

@@ -73,7 +73,8 @@ def _result(sm, infos, rc, **kw):
         seconds=np.array([i.seconds for i in infos]),
         seconds_to_1e6=np.array([i.seconds_to_1e6 for i in infos]),
         rc=rc, wall_seconds=np.array([i.wall_seconds for i in infos]),
-        Ebar=np.array([list(i.Ebar) for i in infos]), **kw)
+        Ebar=np.array([list(i.Ebar) for i in infos]),
+        precision_used=np.array([i.precision_used for i in infos]), **kw)
 
 
 @dataclass
@@ -88,6 +89,7 @@ class SolveResult:
     rc: int
     wall_seconds: np.ndarray | None = None
     Ebar: np.ndarray | None = None             # [n_loads, 6] mean strain of the reported iterate
+    precision_used: np.ndarray | None = None   # [n_loads] HZ_FP64 also for a refinement that fell back
     trace_residual: np.ndarray | None = None   # [n_loads, T]
     trace_mean: np.ndarray | None = None       # [n_loads, T, 6]
     eps: np.ndarray | None = None              # [n_loads, 6, N3, N2, N1]

@@ -127,7 +127,7 @@ void fill_info(const Prob& p, double t0_ms, double wall, hz_info& in) {
   in.status = p.code;
   in.iters = p.iters;
   in.outer_rounds = p.rounds;
-  in.precision_used = p.prec;
+  in.precision_used = p.fb ? HZ_FP64 : p.prec;
   in.residual = p.err;
   in.seconds = 1e-3 * (p.t_done - t0_ms);
   in.seconds_to_1e6 = p.t_1e6 >= 0 ? 1e-3 * (p.t_1e6 - t0_ms) : -1.0;

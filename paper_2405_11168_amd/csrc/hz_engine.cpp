@@ -523,7 +523,9 @@ MaterialTables upload_material_tables(const Material& m, char* dev, hipStream_t 
 size_t prob_bytes(const Shape& s, int prec, bool trace) {
   const size_t S = (size_t)s.geo.S;
   const size_t ub = prec == HZ_FP64 ? 16 : 8;
-  size_t b = align_up(12 * S * 16) + 2 * align_up(3 * S * ub);
+  // FP64: two displacement buffers.  FP32+refine: the two FP32 buffers share one block
+  // of FP64 size (the second FP64 buffer of a fallback to FP64 iterations), then U, r
+  size_t b = align_up(12 * S * 16) + (prec == HZ_FP64 ? 2 * align_up(3 * S * ub) : align_up(3 * S * 16));
   if (prec != HZ_FP64) b += align_up(3 * S * 16) + align_up(3 * S * 8);
   b += align_up((size_t)s.nbx_max() * 6 * 8) + align_up((size_t)s.nbq_max() * 8);
   if (trace) b += align_up((size_t)kTraceCap * 7 * 8);
@@ -541,8 +543,16 @@ ProbBuffers carve_prob(const Shape& s, int prec, bool trace, char* dev) {
     return r;
   };
   b.spec = take(12 * S * 16);
-  b.u0 = take(3 * S * ub);
-  b.u1 = take(3 * S * ub);
+  if (prec == HZ_FP64) {
+    b.u0 = take(3 * S * ub);
+    b.u1 = take(3 * S * ub);
+  } else {
+    // 3 S complex doubles, or two FP32 buffers; u1 starts 3 S complex floats in (S is
+    // even, so a multiple of 16 bytes)
+    char* u = take(3 * S * 16);
+    b.u0 = u;
+    b.u1 = u + 3 * S * 8;
+  }
   if (prec != HZ_FP64) {
     b.u64 = take(3 * S * 16);
     b.r32 = take(3 * S * 8);
@@ -769,7 +779,7 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
   L.done(launch_finalize(e.d_desc, act, n, fg, e.stream), "finalize");
 }
 
-bool kernel_fp64(PState s) { return s == PS_IT64 || s == PS_SWEEP; }
+bool kernel_fp64(PState s) { return s == PS_IT64 || s == PS_SWEEP || s == PS_FB64; }
 
 // material kind in the problem's current state (a correction round has no eigenstress)
 int kind_of(const Prob* p) {
@@ -875,6 +885,17 @@ void Engine::enter_state(Prob* p) {
       d.cmode = 1;
       d.fmode = 1;
       d.src = 1;
+      break;
+    case PS_FB64:
+      // plain FP64 iterations of the full problem from U, ping-ponging between U and the
+      // block of the two FP32 buffers; the rest of the iteration budget
+      d.cmode = 0;
+      d.fmode = 0;
+      d.src = 0;
+      d.u[0] = p->base.u64;
+      d.u[1] = p->base.u[0];
+      d.fixed_iters = -1;
+      d.max_iters = std::max(0, p->max_iters - p->inner_total);
       break;
     case PS_CORR: {
       d.cmode = 2;
@@ -993,6 +1014,7 @@ std::vector<Prob*> Engine::tick() {
       int r = 1;
       if (p->st == PS_IT64) r = (p->fixed_iters >= 0 ? p->fixed_iters : p->max_iters) - p->k0 + 1;
       else if (p->st == PS_R0 || p->st == PS_CORR) r = p->inner_max - p->k0;
+      else if (p->st == PS_FB64) r = std::max(0, p->max_iters - p->inner_total) - p->k0 + 1;
       need = std::max(need, r);
     }
     s.K = std::max(1, std::min(check_every, need));
@@ -1040,6 +1062,13 @@ std::vector<Prob*> Engine::tick() {
       if (p->st == PS_DONE) fin.push_back(p);
     }
   }
+  // a problem that fell back to FP64 iterations reports its iterate through U like every
+  // refined problem: copy it there when it sits in the second buffer
+  for (Prob* p : fin)
+    if (p->fb && p->parity == 1)
+      hip_check(hipMemcpyAsync(p->base.u64, p->base.u[0], (size_t)3 * p->shape->geo.S * 16, hipMemcpyDeviceToDevice,
+                               stream),
+                "fallback iterate to U");
   // a finished stencil-form problem reports u(q): its iterate leaves the mixed domain
   for (Prob* p : fin)
     if (p->form == HZ_SCHEME_STENCIL)
@@ -1099,9 +1128,11 @@ void Engine::advance(Prob* p, const double* s, const double* t_iter) {
       }
       p->inner_total += (int)s[ST_ITERS];
       if (p->st == PS_CORR && flag == 3) {
-        // a correction that blew up leaves U as the last sweep measured it
-        p->code = HZ_STAGNATED;
-        p->st = PS_DONE;
+        // a correction that blew up leaves U as the last sweep measured it; the rest of
+        // the budget runs as plain FP64 iterations from U
+        p->st = PS_FB64;
+        p->fb = true;
+        p->enter = true;
         return;
       }
       // a diverged first estimate keeps U = 0
@@ -1129,11 +1160,14 @@ void Engine::advance(Prob* p, const double* s, const double* t_iter) {
         p->code = HZ_NOT_CONVERGED;
         stop = true;
       } else {
-        // a rounding floor: three sweeps in a row that gained less than 10%
+        // the refinement stopped gaining (three sweeps in a row under 10%): the rest of
+        // the budget runs as plain FP64 iterations from U
         p->slow = p->err > 0.9 * p->prev_err ? p->slow + 1 : 0;
         if (p->slow >= 3) {
-          p->code = HZ_STAGNATED;
-          stop = true;
+          p->st = PS_FB64;
+          p->fb = true;
+          p->enter = true;
+          return;
         }
       }
       if (stop) {
@@ -1145,6 +1179,24 @@ void Engine::advance(Prob* p, const double* s, const double* t_iter) {
       p->sweep_norm = s[ST_NORM];
       p->st = PS_CORR;
       p->enter = true;
+      return;
+    }
+    case PS_FB64: {
+      const int kk0 = p->k0;
+      p->k0 = k1;
+      if (!flag) {
+        if (k1 > std::max(0, p->max_iters - p->inner_total) + 1) fail(HZ_EINVAL, "stop rule did not fire");
+        return;
+      }
+      p->code = flag == 1 ? HZ_OK : (flag == 2 ? HZ_NOT_CONVERGED : HZ_EDIVERGED);
+      p->iters = p->inner_total + (int)s[ST_ITERS];
+      p->parity = (int)s[ST_PARITY];
+      p->err = s[ST_ERR];
+      for (int c = 0; c < 6; ++c) p->mean[c] = s[ST_MEAN + c];
+      for (int c = 0; c < 6; ++c) p->Ebar[c] = s[ST_EBAR + c];
+      p->t_done = t_iter[std::max(0, k1 - 1 - kk0)];
+      if (p->t_1e6 < 0 && p->err < 1e-6) p->t_1e6 = p->t_done;
+      p->st = PS_DONE;
       return;
     }
     default:

@@ -173,7 +173,8 @@ struct Prof {
 };
 
 // ---- one load case of one grid: a state machine advanced by the executor
-enum PState { PS_NEW, PS_IT64, PS_R0, PS_SWEEP, PS_CORR, PS_DONE };
+// PS_FB64: FP64 iterations from the anchor U after the refinement stopped gaining
+enum PState { PS_NEW, PS_IT64, PS_R0, PS_SWEEP, PS_CORR, PS_FB64, PS_DONE };
 
 struct Prob {
   // set by the owner before Engine::add
@@ -199,6 +200,7 @@ struct Prob {
   bool started = false;
   // results
   int code = HZ_OK, iters = 0, rounds = 0, inner_total = 0, slow = 0, parity = 0;
+  bool fb = false;  // the refinement fell back to FP64 iterations (reported as the path used)
   double err = 0, prev_err = 1e300, mean[6]{};
   double sweep_norm = 0;                      // ||<sigma>|| of the last FP64 sweep
   double t_start = 0, t_done = 0, t_1e6 = -1;  // device ms since the executor's clock start

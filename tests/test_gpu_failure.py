@@ -133,3 +133,26 @@ def test_stencil_resume_with_single_pass_z_transforms(shape):
     for name in ("mean_sigma", "eps", "sigma"):
         _same(getattr(b, name), getattr(full, name), False, name)
     _same(g.displacement(0), u9, False, "u")
+
+
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_refinement_falls_back_to_fp64_iterations(scheme):
+    """Percolating stiff spheres (32^3, contrast 1e4): the FP32 corrections stop gaining
+    far above tol, so the solve continues as plain FP64 iterations from U for the rest of
+    its budget and reports HZ_FP64 as the path used; the reported residual is that of the
+    reported displacement (an FP64 solve started from it measures the same eps_0)."""
+    ph, _, _ = syn.boolean_spheres((32, 32, 32), 2.0, 0.3, 11)
+    C = np.stack([syn.isotropic_voigt(1.0, 0.3), syn.isotropic_voigt(1e4, 0.3)])
+    C0 = syn.ref_alpha_rule(1.0, 1e4, 0.3)
+    g = hz.Grid(32, 32, 32)
+    g.set_material(C, ph)
+    E = np.array([syn.unit_load(0)])
+    r = g.solve(E, C0=C0, tol=1e-8, precision=hz.HZ_FP32_REFINE, max_iters=3000, scheme=scheme)
+    _say(f"  status {r.status[0]} path {r.precision_used[0]} iters {r.iters[0]} rounds {r.outer_rounds[0]} "
+         f"residual {r.residual[0]:.3e}")
+    assert r.precision_used[0] == hz.HZ_FP64
+    assert r.status[0] in (hz.HZ_OK, hz.HZ_NOT_CONVERGED) and r.iters[0] <= 3000
+    u = g.displacement(0)[None]
+    chk = g.solve(E, C0=C0, fixed_iters=0, trace=True, u_init=u, scheme=scheme)
+    assert abs(chk.trace_residual[0, 0] - r.residual[0]) <= 1e-9 * r.residual[0]
+    assert np.abs(chk.mean_sigma[0] - r.mean_sigma[0]).max() <= 1e-9 * np.abs(r.mean_sigma[0]).max()
