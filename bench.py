@@ -230,6 +230,7 @@ def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5):
                       "p50_converged_s": round(float(np.percentile(lat[ok], 50)), 4) if ok.any() else None,
                       "p99_converged_s": round(float(np.percentile(lat[ok], 99)), 4) if ok.any() else None},
         "status_counts": {names.get(int(c), str(int(c))): int((status == c).sum()) for c in np.unique(status)},
+        "fp64_fallbacks": int(sum(int(r.precision_used[0]) == hz.HZ_FP64 for r in res)),
         "mean_fp32_iters": round(float(iters.mean()), 1),
         "voxel_iters_per_s_closed_loop": float((vox * iters).sum() / makespan),
         "arena_gib": round(arena / 2 ** 30, 2), "generation_s": round(gen_s, 1),
