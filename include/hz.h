@@ -52,9 +52,10 @@ extern "C" {
 
 #define HZ_OK 0
 #define HZ_NOT_CONVERGED 1   /* max_iters reached; outputs written from the last iterate  */
-#define HZ_STAGNATED 2       /* reserved: a refinement that stops gaining (3 FP64 sweeps in
-                                a row under 10%, or a correction that diverges) continues
-                                as plain FP64 iterations from U (hz_info.precision_used)  */
+#define HZ_STAGNATED 2       /* reserved, not returned: a refinement that stops gaining (3
+                                FP64 sweeps in a row under 10%, or a correction that
+                                diverges) continues as plain FP64 iterations from its FP64
+                                anchor U instead (hz_info.precision_used = HZ_FP64)        */
 #define HZ_PENDING 3         /* hz_server_query: the request has not finished yet          */
 #define HZ_EINVAL (-1)       /* NULL pointer, size <= 0, unsupported size or option        */
 #define HZ_EODD (-2)         /* a grid dimension is odd (the scheme needs even N_i)        */
@@ -102,13 +103,16 @@ typedef struct hz_grid_s* hz_grid;
 
 typedef struct {
   double tol;               /* stop at the first iterate k with eps_k < tol (eq. tolerance)   */
-  int32_t max_iters;        /* cap on updates (FP64) or on FP32 inner updates (refinement)     */
+  int32_t max_iters;        /* cap on updates, <= 1000000 (<= 4096 with a trace): FP64 updates,
+                               or for HZ_FP32_REFINE the FP32 inner updates plus the FP64
+                               updates of a fallback to plain FP64 iterations                 */
   int32_t precision;        /* HZ_FP64 or HZ_FP32_REFINE                                        */
   int32_t ref_mode;         /* 0: automatic reference medium; 1: use ref_C                      */
   double ref_C[36];         /* reference medium lambda0, Voigt 6x6, when ref_mode = 1           */
   int32_t fixed_iters;      /* >= 0: run exactly this many updates, ignore tol (parity tests)   */
   int32_t check_every;      /* host looks at the device stop flags every this many iterations  */
-  double* trace_residual;   /* optional [n_loads][max_iters+1]: eps_k of every iterate (FP64)   */
+  double* trace_residual;   /* optional [n_loads][max_iters+1]: eps_k of every iterate (FP64);
+                               needs max_iters (or fixed_iters) <= 4096                       */
   double* trace_mean;       /* optional [n_loads][max_iters+1][6]: <sigma>_k                    */
   double inner_rho;         /* refinement: inner loop stops at rho * eps of its FP64 sweep      */
   int32_t inner_max;        /* refinement: cap on inner iterations per outer round              */
@@ -124,6 +128,9 @@ typedef struct {
                                iterates                                                         */
   const double* Ebar_init;  /* optional [n_loads][6]: under HZ_LOAD_STRESS, the mean strain of
                                iterate 0 (hz_info.Ebar of the checkpoint); NULL: lambda0^-1:sigma^a */
+  int32_t fields_on_device; /* 0: eps_out / sig_out of hz_solve are host arrays; 1: device
+                               arrays (caller-owned, 8-byte aligned), written on the bound
+                               stream before hz_solve returns                                  */
 } hz_opts;
 
 typedef struct {
@@ -134,7 +141,8 @@ typedef struct {
                                fell back to FP64 iterations for the rest of its budget          */
   double residual;          /* eps of the reported iterate, measured in FP64                    */
   double seconds;           /* device time from solve start to the reported iterate            */
-  double seconds_to_1e6;    /* device time to the first FP64-verified eps < 1e-6, or -1         */
+  double seconds_to_1e6;    /* device time to the first FP64-verified eps < 1e-6 (an FP64
+                               iterate or an FP64 sweep of the refinement), or -1             */
   double wall_seconds;      /* host wall time: the hz_solve call, or a served request from
                                submission to the step that saw it finish (queueing included)     */
   double Ebar[6];           /* mean strain of the reported iterate (tensor comps): the applied
@@ -143,17 +151,22 @@ typedef struct {
 
 /* Fill *o with defaults: tol 1e-8, max_iters 2000, HZ_FP64, automatic reference,
  * fixed_iters -1, check_every 8, no traces, inner_rho 1e-3, inner_max 400,
- * HZ_SCHEME_AUTO, HZ_LOAD_STRAIN, no initial guess. */
+ * HZ_SCHEME_AUTO, HZ_LOAD_STRAIN, no initial guess, host field outputs. */
 void hz_default_opts(hz_opts* o);
 
 /* Create a grid handle for an n1 x n2 x n3 periodic cell (Sec. 2.1).
  * Returns HZ_EODD for an odd size, HZ_EINVAL for other unsupported sizes. */
 int hz_create_grid(int32_t n1, int32_t n2, int32_t n3, hz_grid* out);
 
-/* Set the microstructure: n_phases stiffness matrices C_voigt[n_phases][6][6]
- * and the phase id of every voxel phase[n3][n2][n1] (< n_phases).  Zero
- * stiffness (voids) is allowed.  Host arrays are copied; device copies are made
- * by hz_bind_workspace.  Clears eigenstrains set before. */
+/* Set the microstructure: the stiffness field lambda(r) of the constitutive law
+ * sigma = lambda(r):(eps - eps0) (eq. linear_elasticity, Sec. 2.1), piecewise
+ * constant over the voxels of the simple-cubic grid, as n_phases stiffness matrices
+ * C_voigt[n_phases][6][6] and the phase id of every voxel phase[n3][n2][n1]
+ * (< n_phases).  Each matrix must be symmetric and positive semi-definite
+ * (HZ_ENOTSPD otherwise); zero stiffness (voids) is allowed.  Host arrays are
+ * copied; device copies are made by hz_bind_workspace.  Clears eigenstrains set
+ * before.  HZ_EINVAL for NULL pointers, n_phases outside [1, 65536] or a phase id
+ * out of range. */
 int hz_set_material(hz_grid g, int32_t n_phases, const double* C_voigt, const uint16_t* phase);
 
 /* Per-phase eigenstrains eps0[n_phases][6] (tensor comps; eq. linear_elasticity:
@@ -180,16 +193,18 @@ int hz_bind_workspace(hz_grid g, void* dev_ptr, int64_t bytes, void* hip_stream,
  * Sec. 2.5), tensor comps.
  * Outputs (each may be NULL):
  *   sigma_mean[n_loads][6]  <sigma> of the reported iterate (FP64)
- *   eps_out, sig_out        host [n_loads][6][n3][n2][n1] FP64 fields of eq. final_fields
+ *   eps_out, sig_out        [n_loads][6][n3][n2][n1] FP64 fields of eq. final_fields,
+ *                           host arrays, or device arrays with o->fields_on_device
  *   info[n_loads]
  * Returns the worst per-load status (negative codes first). */
 int hz_solve(hz_grid g, int32_t n_loads, const double* E, const hz_opts* o,
              double* sigma_mean, double* eps_out, double* sig_out, hz_info* info);
 
 /* Effective stiffness: the six unit load cases (gamma_J = 1) solved as one batch;
- * column J of C_eff (row-major 6x6 Voigt) is <sigma> of case J.  Needs a workspace
- * bound for n_loads >= 6, strain loading and a material without eigenstrains
- * (HZ_EINVAL otherwise). */
+ * column J of C_eff (row-major 6x6 engineering Voigt) is <sigma> of case J, the
+ * volume average of the stress field of eq. final_fields at the reported iterate.
+ * Needs a workspace bound for n_loads >= 6, strain loading and a material without
+ * eigenstrains (HZ_EINVAL otherwise).  info may be NULL; traces in *o are [6][...]. */
 int hz_effective_stiffness(hz_grid g, const hz_opts* o, double C_eff[36], hz_info info[6]);
 
 /* Copy the displacement spectrum of load `load` after the last solve to host:

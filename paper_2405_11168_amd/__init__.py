@@ -163,53 +163,75 @@ class Grid:
             self.bind(precision, n_loads)
 
     # -- solve -----------------------------------------------------------------
-    def solve(self, E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1,
-              fields=False, trace=False, check_every=8, inner_rho=1e-3, inner_max=400,
-              scheme=HZ_SCHEME_AUTO, loading=HZ_LOAD_STRAIN, u_init=None, Ebar_init=None) -> SolveResult:
-        """E: [n_loads, 6] applied mean strains, or applied stresses with loading=HZ_LOAD_STRESS.
-        u_init: optional [n_loads, 3, N1/2+1, N3, N2] complex displacement of iterate 0 (as
-        returned by displacement()); Ebar_init: optional [n_loads, 6] mean strain of iterate 0
-        under applied stress.  Together they resume a solve from a checkpoint."""
-        E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
-        nl = E.shape[0]
+    def _prepare(self, nl, tol, max_iters, precision, C0, fixed_iters, trace, check_every, inner_rho, inner_max,
+                 scheme, loading, u_init, Ebar_init):
+        """Options struct and the host arrays it points to (kept alive by the caller)."""
         self._ensure(precision, 2 * nl if scheme == HZ_SCHEME_STRAIN else nl)
         o = _opts(tol, max_iters, precision, C0, fixed_iters, check_every, inner_rho, inner_max, scheme, loading)
         T = (fixed_iters if fixed_iters >= 0 else max_iters) + 1
-        tr = tm = None
+        keep = {}
         if trace:
-            tr = np.full((nl, T), np.nan)
-            tm = np.full((nl, T, 6), np.nan)
-            o.trace_residual = _dptr(tr)
-            o.trace_mean = _dptr(tm)
-        keep = []
+            keep["tr"] = np.full((nl, T), np.nan)
+            keep["tm"] = np.full((nl, T, 6), np.nan)
+            o.trace_residual = _dptr(keep["tr"])
+            o.trace_mean = _dptr(keep["tm"])
         if u_init is not None:
             n1, n2, n3 = self.shape
             u = np.asarray(u_init, dtype=np.complex128).reshape(nl, 3, n1 // 2 + 1, n3, n2)
-            ui = np.ascontiguousarray(np.stack([u.real, u.imag], axis=-1))
-            keep.append(ui)
-            o.u_init = _dptr(ui)
+            keep["ui"] = np.ascontiguousarray(np.stack([u.real, u.imag], axis=-1))
+            o.u_init = _dptr(keep["ui"])
         if Ebar_init is not None:
-            eb = np.ascontiguousarray(np.asarray(Ebar_init, dtype=np.float64).reshape(nl, 6))
-            keep.append(eb)
-            o.Ebar_init = _dptr(eb)
+            keep["eb"] = np.ascontiguousarray(np.asarray(Ebar_init, dtype=np.float64).reshape(nl, 6))
+            o.Ebar_init = _dptr(keep["eb"])
+        return o, keep
+
+    def solve(self, E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1,
+              fields=False, trace=False, check_every=8, inner_rho=1e-3, inner_max=400,
+              scheme=HZ_SCHEME_AUTO, loading=HZ_LOAD_STRAIN, u_init=None, Ebar_init=None,
+              fields_on_device=False) -> SolveResult:
+        """E: [n_loads, 6] applied mean strains, or applied stresses with loading=HZ_LOAD_STRESS.
+        u_init: optional [n_loads, 3, N1/2+1, N3, N2] complex displacement of iterate 0 (as
+        returned by displacement()); Ebar_init: optional [n_loads, 6] mean strain of iterate 0
+        under applied stress.  Together they resume a solve from a checkpoint.
+        fields=True returns eps, sigma [n_loads, 6, N3, N2, N1] as numpy arrays, or with
+        fields_on_device=True as float64 torch tensors on the workspace's device, written
+        there by the library (no host round trip)."""
+        E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
+        nl = E.shape[0]
+        o, keep = self._prepare(nl, tol, max_iters, precision, C0, fixed_iters, trace, check_every, inner_rho,
+                                inner_max, scheme, loading, u_init, Ebar_init)
         sm = np.zeros((nl, 6))
         infos = (hz_info * nl)()
         n1, n2, n3 = self.shape
         eps = sig = None
-        if fields:
+        pe = ps = None
+        if fields and fields_on_device:
+            import torch
+
+            eps = torch.empty((nl, 6, n3, n2, n1), dtype=torch.float64, device=self._ws.device)
+            sig = torch.empty_like(eps)
+            o.fields_on_device = 1
+            pe = ctypes.cast(ctypes.c_void_p(eps.data_ptr()), ctypes.POINTER(ctypes.c_double))
+            ps = ctypes.cast(ctypes.c_void_p(sig.data_ptr()), ctypes.POINTER(ctypes.c_double))
+        elif fields:
             eps = np.zeros((nl, 6, n3, n2, n1))
             sig = np.zeros((nl, 6, n3, n2, n1))
-        rc = _outcome(lib().hz_solve(self._h, nl, _dptr(E), ctypes.byref(o), _dptr(sm),
-                                     _dptr(eps) if fields else None, _dptr(sig) if fields else None, infos))
-        return _result(sm, infos, rc, trace_residual=tr, trace_mean=tm, eps=eps, sigma=sig)
+            pe, ps = _dptr(eps), _dptr(sig)
+        rc = _outcome(lib().hz_solve(self._h, nl, _dptr(E), ctypes.byref(o), _dptr(sm), pe, ps, infos))
+        return _result(sm, infos, rc, trace_residual=keep.get("tr"), trace_mean=keep.get("tm"), eps=eps, sigma=sig)
 
-    def effective_stiffness(self, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, **kw):
-        """C_eff (6x6 Voigt): column J = <sigma> of unit load gamma_J = 1, six loads in one batch."""
-        E = np.zeros((6, 6))
-        for J in range(6):
-            E[J, J] = 1.0 if J < 3 else 0.5
-        r = self.solve(E, tol=tol, max_iters=max_iters, precision=precision, C0=C0, **kw)
-        return r.mean_sigma.T.copy(), r
+    def effective_stiffness(self, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1,
+                            trace=False, check_every=8, inner_rho=1e-3, inner_max=400, scheme=HZ_SCHEME_AUTO):
+        """C_eff (6x6 Voigt) by hz_effective_stiffness: column J = <sigma> of the unit load
+        gamma_J = 1, the six loads solved as one batch.  Returns (C_eff, SolveResult of the
+        six loads in the order J = 0..5)."""
+        o, keep = self._prepare(6, tol, max_iters, precision, C0, fixed_iters, trace, check_every, inner_rho,
+                                inner_max, scheme, HZ_LOAD_STRAIN, None, None)
+        Ce = np.zeros(36)
+        infos = (hz_info * 6)()
+        rc = _outcome(lib().hz_effective_stiffness(self._h, ctypes.byref(o), _dptr(Ce), infos))
+        Ce = Ce.reshape(6, 6)
+        return Ce, _result(Ce.T.copy(), infos, rc, trace_residual=keep.get("tr"), trace_mean=keep.get("tm"))
 
     def scheme_available(self, scheme) -> bool:
         return bool(check(lib().hz_scheme_available(self._h, scheme)))

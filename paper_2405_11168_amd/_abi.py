@@ -47,6 +47,7 @@ class hz_opts(ctypes.Structure):
         ("loading", c_int32),
         ("u_init", POINTER(c_double)),
         ("Ebar_init", POINTER(c_double)),
+        ("fields_on_device", c_int32),
     ]
 
 

@@ -30,8 +30,11 @@ thread_local std::string g_err;
 void check_opts(const hz_opts& o) {
   if (o.precision != HZ_FP64 && o.precision != HZ_FP32_REFINE) fail(HZ_EINVAL, "unknown precision");
   if (!(o.tol > 0) && o.fixed_iters < 0) fail(HZ_EINVAL, "tol must be > 0");
-  if (o.max_iters < 0 || o.max_iters > kTraceCap - 1) fail(HZ_EINVAL, "max_iters out of range [0, 4096]");
-  if (o.fixed_iters > kTraceCap - 1) fail(HZ_EINVAL, "fixed_iters out of range");
+  if (o.max_iters < 0 || o.max_iters > kMaxIters) fail(HZ_EINVAL, "max_iters out of range [0, 1000000]");
+  if (o.fixed_iters > kTraceCap - 1) fail(HZ_EINVAL, "fixed_iters out of range [0, 4096]");
+  if ((o.trace_residual || o.trace_mean) && o.fixed_iters < 0 && o.max_iters > kTraceCap - 1)
+    fail(HZ_EINVAL, "a trace needs max_iters <= 4096");
+  if (o.fields_on_device != 0 && o.fields_on_device != 1) fail(HZ_EINVAL, "fields_on_device must be 0 or 1");
   if (o.inner_max < 0 || o.inner_max > 100000) fail(HZ_EINVAL, "inner_max out of range");
   if (o.scheme < HZ_SCHEME_AUTO || o.scheme > HZ_SCHEME_STRAIN) fail(HZ_EINVAL, "unknown scheme");
   if (o.scheme == HZ_SCHEME_STRAIN && o.precision != HZ_FP64) fail(HZ_EINVAL, "the strain-based scheme needs HZ_FP64");
@@ -266,8 +269,14 @@ int grid_solve(hz_grid g, int nl, const double* E, const hz_opts& o, double* sig
   if (eps_out || sig_out) {
     const size_t n6 = (size_t)6 * g->shape.geo.N;
     double* fe = reinterpret_cast<double*>(g->ws + g->off.fields);
+    const bool dev = o.fields_on_device != 0;
     for (int b = 0; b < nl; ++b) {
-      output_fields(e, g->probs[b], fe, fe + n6);
+      // device outputs are written by the field writer in place; host outputs (and an
+      // output the caller did not ask for) go through the workspace's field buffer
+      double* de = dev && eps_out ? eps_out + (size_t)b * n6 : fe;
+      double* ds = dev && sig_out ? sig_out + (size_t)b * n6 : fe + n6;
+      output_fields(e, g->probs[b], de, ds);
+      if (dev) continue;
       if (eps_out)
         hip_check(hipMemcpy(eps_out + (size_t)b * n6, fe, n6 * 8, hipMemcpyDeviceToHost), "eps D2H");
       if (sig_out)

@@ -856,6 +856,7 @@ void Engine::enter_state(Prob* p) {
   d.status = d_status + (size_t)p->slot * kStatusLen;
   double* s = h_status + (size_t)p->slot * kStatusLen;
   std::fill(s, s + kStatusLen, 0.0);
+  s[ST_K1E6] = -1.0;
   d.trace = nullptr;
   d.trace_len = 0;
   d.tol = p->tol;
@@ -1086,13 +1087,6 @@ std::vector<Prob*> Engine::tick() {
     }
   if (copied) hip_check(hipStreamSynchronize(stream), "sync");
   if (prof->on) prof->drain();
-  for (Prob* p : fin)
-    if (!p->trace.empty())
-      for (int t = 0; t * 7 < (int)p->trace.size() && t < (int)p->times.size(); ++t)
-        if (p->trace[(size_t)t * 7] < 1e-6) {
-          p->t_1e6 = p->times[t];
-          break;
-        }
   live.erase(std::remove_if(live.begin(), live.end(), [](Prob* p) { return p->st == PS_DONE; }), live.end());
   return fin;
 }
@@ -1104,6 +1098,9 @@ void Engine::advance(Prob* p, const double* s, const double* t_iter) {
     case PS_IT64: {
       for (int t = p->k0; t < k1; ++t) p->times.push_back(t_iter[t - p->k0]);
       p->k0 = k1;
+      // the device records the first iterate below 1e-6; map it to its event
+      const int k6 = (int)s[ST_K1E6];
+      if (p->t_1e6 < 0 && k6 >= 0 && k6 < (int)p->times.size()) p->t_1e6 = p->times[k6];
       if (!flag) {
         const int cap_it = p->fixed_iters >= 0 ? p->fixed_iters : p->max_iters;
         if (k1 > cap_it + 1) fail(HZ_EINVAL, "stop rule did not fire");
@@ -1184,6 +1181,8 @@ void Engine::advance(Prob* p, const double* s, const double* t_iter) {
     case PS_FB64: {
       const int kk0 = p->k0;
       p->k0 = k1;
+      const int k6 = (int)s[ST_K1E6];
+      if (p->t_1e6 < 0 && k6 >= kk0 && k6 < k1) p->t_1e6 = t_iter[k6 - kk0];
       if (!flag) {
         if (k1 > std::max(0, p->max_iters - p->inner_total) + 1) fail(HZ_EINVAL, "stop rule did not fire");
         return;
@@ -1195,7 +1194,6 @@ void Engine::advance(Prob* p, const double* s, const double* t_iter) {
       for (int c = 0; c < 6; ++c) p->mean[c] = s[ST_MEAN + c];
       for (int c = 0; c < 6; ++c) p->Ebar[c] = s[ST_EBAR + c];
       p->t_done = t_iter[std::max(0, k1 - 1 - kk0)];
-      if (p->t_1e6 < 0 && p->err < 1e-6) p->t_1e6 = p->t_done;
       p->st = PS_DONE;
       return;
     }

@@ -56,6 +56,7 @@ void hip_check(hipError_t e, const char* what);
 #endif
 
 constexpr int kTraceCap = 4097;        // iterates recorded per load (eps_k, <sigma>_k)
+constexpr int kMaxIters = 1000000;     // cap on max_iters
 constexpr int kLdsBytes = 65536 - 512;  // LDS budget of one work-group
 
 float recip(int d);

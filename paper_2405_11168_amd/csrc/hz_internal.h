@@ -92,6 +92,7 @@ enum St {
   ST_EBAR = 16,      // 16..21 mean strain Ebar of the current iterate (tensor comps): the
                      // applied strain, zero in a correction round, or under applied stress
                      // the iterate of the loop on the mean strain (updated on the device)
+  ST_K1E6 = 22,      // FP64 iterations: first iterate k with eps_k < 1e-6 in this state, or -1
 };
 constexpr int kStatusLen = 24;
 

@@ -142,6 +142,37 @@ def test_sphere16_converged_ceff_matches_oracle_iterate_matched():
     assert err < 1e-10
 
 
+def test_effective_stiffness_entry_equals_six_unit_solves_bitwise():
+    """hz_effective_stiffness (the C-ABI call Grid.effective_stiffness makes) returns as
+    column J exactly <sigma> of hz_solve on the unit load gamma_J = 1."""
+    ph, C, C0, _ = random_problem((16, 12, 10), 3, 31, "aniso")
+    g = hz.Grid(16, 12, 10)
+    g.set_material(C, ph)
+    for prec in (hz.HZ_FP64, hz.HZ_FP32_REFINE):
+        Ce, r = g.effective_stiffness(tol=1e-9, C0=C0, precision=prec)
+        E = np.array([syn.unit_load(J) for J in range(6)])
+        rs = g.solve(E, tol=1e-9, C0=C0, precision=prec)
+        assert np.array_equal(Ce, rs.mean_sigma.T), prec
+        assert np.array_equal(r.iters, rs.iters) and np.array_equal(r.residual, rs.residual)
+        asym = np.abs(Ce - Ce.T).max() / np.abs(Ce).max()
+        _say(f"  C_eff precision {prec}: iters {r.iters}, symmetry residual {asym:.1e}")
+        assert asym < 1e-7
+
+
+def test_device_field_outputs_equal_host_outputs():
+    """fields_on_device: eps and sigma written into caller-owned device arrays equal the
+    host outputs bit for bit, for a batch of loads in both forms."""
+    ph, C, C0, E = random_problem((16, 12, 10), 2, 32, "aniso")
+    E = np.vstack([E, 0.5 * E[:, ::-1]])
+    g = hz.Grid(16, 12, 10)
+    g.set_material(C, ph)
+    for scheme in SCHEMES:
+        rh = g.solve(E, C0=C0, fixed_iters=5, fields=True, scheme=scheme)
+        rd = g.solve(E, C0=C0, fixed_iters=5, fields=True, fields_on_device=True, scheme=scheme)
+        assert rd.eps.is_cuda and rd.eps.shape == rh.eps.shape
+        assert np.array_equal(rd.eps.cpu().numpy(), rh.eps) and np.array_equal(rd.sigma.cpu().numpy(), rh.sigma)
+
+
 def test_batched_loads_equal_single_loads_bitwise():
     ph, C, C0, _ = random_problem((12, 10, 8), 3, 7, "aniso")
     E = np.array([syn.unit_load(J) for J in range(6)]) * 1e-3
@@ -154,10 +185,17 @@ def test_batched_loads_equal_single_loads_bitwise():
         assert np.array_equal(rs.mean_sigma[0], rb.mean_sigma[J])
 
 
+def _u_err(g, J, ref, shape):
+    """max |u_gpu - u_oracle| / max |u_oracle| over the whole half spectrum of load J."""
+    uo = oracle_u_in_library_layout(ref.u_hat, shape)
+    return np.abs(g.displacement(J) - uo).max() / np.abs(uo).max()
+
+
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
 def test_full_size_boolean128_first_iterates(scheme):
     """The 128^3 Boolean-sphere workload (contrast 1e3, 6 loads) in the launch
-    configuration the benchmark times: iterates 0..2 of two loads vs the oracle."""
+    configuration the benchmark times: iterates 0..2 of two loads vs the oracle,
+    residual and <sigma> at every iterate and the displacement u_2 element by element."""
     p = syn.boolean128()
     g = hz.Grid(*p.shape)
     g.set_material(p.C, p.phase)
@@ -167,8 +205,27 @@ def test_full_size_boolean128_first_iterates(scheme):
         ref = tetra.basic_scheme(p.phase, p.C, p.C0, p.loads[J], fixed_iters=K, keep_fields=False)
         eh = np.max(np.abs(r.trace_residual[J, : K + 1] - ref.history) / ref.history)
         em = np.abs(r.trace_mean[J, : K + 1] - ref.mean_history).max() / np.abs(ref.mean_history).max()
-        _say(f"  boolean128 load {J}: residual hist {eh:.2e} <sigma> {em:.2e}")
-        assert eh < 1e-10 and em < 1e-12
+        eu = _u_err(g, J, ref, p.shape)
+        _say(f"  boolean128 load {J}: residual hist {eh:.2e} <sigma> {em:.2e} u {eu:.2e}")
+        assert eh < 1e-10 and em < 1e-12 and eu < 1e-11
+
+
+def test_full_size_boolean128_fields_one_load():
+    """The 128^3 workload: the fields of eq. final_fields of one load after 2 updates,
+    every voxel and component against the oracle (host and device outputs)."""
+    p = syn.boolean128()
+    g = hz.Grid(*p.shape)
+    g.set_material(p.C, p.phase)
+    K = 2
+    E = p.loads[:1]
+    r = g.solve(E, C0=p.C0, fixed_iters=K, fields=True)
+    rd = g.solve(E, C0=p.C0, fixed_iters=K, fields=True, fields_on_device=True)
+    ref = tetra.basic_scheme(p.phase, p.C, p.C0, E[0], fixed_iters=K, keep_fields=True)
+    es = np.abs(r.sigma[0] - ref.sigma).max() / np.abs(ref.sigma).max()
+    ee = np.abs(r.eps[0] - ref.eps).max() / np.abs(ref.eps).max()
+    _say(f"  boolean128 fields: sigma {es:.2e} eps {ee:.2e}")
+    assert es < 1e-11 and ee < 1e-11
+    assert np.array_equal(rd.eps.cpu().numpy(), r.eps) and np.array_equal(rd.sigma.cpu().numpy(), r.sigma)
 
 
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
@@ -218,8 +275,9 @@ def test_large_non_power_of_two_cell_first_iterates(scheme):
     ref = tetra.basic_scheme(p.phase, p.C, p.C0, E[0], fixed_iters=K, keep_fields=False)
     eh = np.max(np.abs(r.trace_residual[0, : K + 1] - ref.history) / ref.history)
     em = np.abs(r.trace_mean[0, : K + 1] - ref.mean_history).max() / np.abs(ref.mean_history).max()
-    _say(f"  192x192x320: residual hist {eh:.2e} <sigma> {em:.2e}")
-    assert eh < 1e-10 and em < 1e-12
+    eu = _u_err(g, 0, ref, p.shape)
+    _say(f"  192x192x320: residual hist {eh:.2e} <sigma> {em:.2e} u {eu:.2e}")
+    assert eh < 1e-10 and em < 1e-12 and eu < 1e-11
 
 
 def _full_size_iterates_both_forms(p, E, K, label):
@@ -234,8 +292,9 @@ def _full_size_iterates_both_forms(p, E, K, label):
         r = g.solve(E, C0=p.C0, fixed_iters=K, trace=True, scheme=scheme)
         eh = np.max(np.abs(r.trace_residual[0, : K + 1] - ref.history) / ref.history)
         em = np.abs(r.trace_mean[0, : K + 1] - ref.mean_history).max() / np.abs(ref.mean_history).max()
-        _say(f"  {label} scheme {scheme}: residual hist {eh:.2e} <sigma> {em:.2e}")
-        assert eh < 1e-10 and em < 1e-12
+        eu = _u_err(g, 0, ref, p.shape)
+        _say(f"  {label} scheme {scheme}: residual hist {eh:.2e} <sigma> {em:.2e} u {eu:.2e}")
+        assert eh < 1e-10 and em < 1e-12 and eu < 1e-11
 
 
 def test_voronoi256_polycrystal_first_iterates():

@@ -146,3 +146,60 @@ def test_release_of_queued_request_and_errors():
     with pytest.raises(hz.HzError) as e:
         srv.submit(g, _loads(2, 3), tol=1e-6)  # two loads never fit
     assert e.value.code == hz._abi.HZ_EWORKSPACE
+
+
+KINDS = [("iso", False, False), ("iso_eig", False, True), ("aniso", True, False), ("aniso_eig", True, True)]
+
+
+def test_served_requests_match_the_oracle_for_every_material_kind():
+    """One FP64 and one FP32+refine request per material kind (isotropic or anisotropic
+    phases, with or without eigenstrains), served together in one mix.  FP64: <sigma> and
+    the residual at the served stop iterate against the oracle run to that iterate
+    (<= 1e-10 relative).  FP32+refine: <sigma> within 1e-6 of the converged oracle."""
+    from oracle import tetra
+
+    shape = (16, 12, 10)
+    grids, probs = [], []
+    for i, (name, aniso, eig) in enumerate(KINDS):
+        rng = np.random.default_rng(300 + i)
+        N1, N2, N3 = shape
+        ph = rng.integers(0, 3, (N3, N2, N1)).astype(np.uint16)
+        if aniso:
+            C = np.stack([syn.random_spd_voigt(rng, 0.5, 8.0) for _ in range(3)])
+        else:
+            C = np.stack([syn.isotropic_voigt(float(E), 0.3) for E in 10.0 ** rng.uniform(0, 1.5, 3)])
+        s = np.array([1, 1, 1, 2 ** .5, 2 ** .5, 2 ** .5])
+        C0 = syn.isotropic_voigt(0.75 * max(np.linalg.eigvalsh(c * np.outer(s, s)).max() for c in C), 0.0)
+        e0 = rng.normal(size=(3, 6)) * 2e-3 if eig else None
+        g = hz.Grid(*shape)
+        g.set_material(C, ph)
+        if eig:
+            g.set_eigenstrain(e0)
+        grids.append(g)
+        probs.append((ph, C, C0, e0, _loads(1, 400 + i)))
+    need = sum(hz.request_bytes(g, p, 1) for g in grids for p in (hz.HZ_FP64, hz.HZ_FP32_REFINE))
+    srv = hz.Server(int(1.2 * need), max_problems=16, check_every=4)
+    ids = []
+    for g, (ph, C, C0, e0, E) in zip(grids, probs):
+        ids.append((srv.submit(g, E, tol=1e-8, C0=C0, precision=hz.HZ_FP64),
+                    srv.submit(g, E, tol=1e-8, C0=C0, precision=hz.HZ_FP32_REFINE)))
+    srv.drain()
+    for (name, _a, _e), (i64, i32), (ph, C, C0, e0, E) in zip(KINDS, ids, probs):
+        r64 = srv.result(i64)
+        r32 = srv.result(i32)
+        assert r64.status[0] == hz.HZ_OK and r32.status[0] == hz.HZ_OK, name
+        k = int(r64.iters[0])
+        ref = tetra.basic_scheme(ph, C, C0, E[0], fixed_iters=k, eps0=e0, keep_fields=False)
+        scale = np.abs(ref.mean_sigma).max()
+        em = np.abs(r64.mean_sigma[0] - ref.mean_sigma).max() / scale
+        # the residual of a converged iterate is a norm of r(q), a difference of terms of
+        # the size of the stress: rounding is measured against the first residual's scale
+        eh = abs(r64.residual[0] - ref.history[k]) / ref.history[0]
+        conv = tetra.basic_scheme(ph, C, C0, E[0], tol=1e-12, eps0=e0, keep_fields=False)
+        e32 = np.abs(r32.mean_sigma[0] - conv.mean_sigma).max() / np.abs(conv.mean_sigma).max()
+        _say(f"  served {name}: FP64 stop iterate {k} (oracle first below tol: "
+             f"{int(np.argmax(ref.history < 1e-8)) if (ref.history < 1e-8).any() else None}), "
+             f"<sigma> {em:.1e}, residual {eh:.1e}; FP32+refine vs converged {e32:.1e}")
+        assert ref.history[k] < 1e-8 and (k == 0 or ref.history[k - 1] >= 1e-8 * (1 - 1e-9))
+        assert em < 1e-10 and eh < 1e-10
+        assert e32 < 1e-6
