@@ -200,6 +200,23 @@ int hz_bind_workspace(hz_grid g, void* dev_ptr, int64_t bytes, void* hip_stream,
 int hz_solve(hz_grid g, int32_t n_loads, const double* E, const hz_opts* o,
              double* sigma_mean, double* eps_out, double* sig_out, hz_info* info);
 
+/* hz_solve on the library's own static device workspace instead of a bound one, for
+ * callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Same arguments, outputs and
+ * status as hz_solve, plus the HIP stream (hipStream_t of the current device, may be
+ * NULL) the work is issued on.  No workspace needs to be bound; the grid's own
+ * binding, and the loads hz_get_displacement reads, are left as they were.
+ * Memory: one static array of 256 MiB per GPU (allocated when the library's code is
+ * loaded on that device, held until the process ends); the problem must fit it,
+ * i.e. hz_workspace_bytes(g, o->precision, n_loads) (2 n_loads for
+ * HZ_SCHEME_STRAIN) <= 268435456, else HZ_EWORKSPACE.  The call uses no device or
+ * pinned-host allocator (no hipMalloc, hipHostMalloc, hipFree); host bookkeeping uses
+ * the C++ heap.  Every call on one GPU shares that GPU's array, which keeps the last
+ * call's contents (each solve clears what it needs zeroed itself): calls that overlap
+ * on one GPU, from several threads or on several streams, race. */
+int hz_solve_static(hz_grid g, void* hip_stream, int32_t n_loads, const double* E, const hz_opts* o,
+                    double* sigma_mean, double* eps_out, double* sig_out, hz_info* info);
+
 /* Effective stiffness: the six unit load cases (gamma_J = 1) solved as one batch;
  * column J of C_eff (row-major 6x6 engineering Voigt) is <sigma> of case J, the
  * volume average of the stress field of eq. final_fields at the reported iterate.

@@ -75,6 +75,8 @@ SIGNATURES = {
     "hz_bind_workspace": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_int32]),
     "hz_solve": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(hz_opts), POINTER(c_double),
                            POINTER(c_double), POINTER(c_double), POINTER(hz_info)]),
+    "hz_solve_static": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(c_double), POINTER(hz_opts),
+                                  POINTER(c_double), POINTER(c_double), POINTER(c_double), POINTER(hz_info)]),
     "hz_effective_stiffness": (c_int32, [c_void_p, POINTER(hz_opts), POINTER(c_double), POINTER(hz_info)]),
     "hz_get_displacement": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "hz_reference_medium": (c_int32, [c_int32, POINTER(c_double), POINTER(c_double)]),

@@ -15,6 +15,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -201,6 +202,7 @@ struct hz_grid_s {
   ShapeTables tab{};
   MaterialTables mtab{};
   std::unique_ptr<Engine> eng;
+  std::unique_ptr<Engine> seng;  // executor of hz_solve_static (pageable host mirrors)
   Prof prof;
   std::vector<Prob> probs;
   int last_prec = -1;
@@ -432,6 +434,71 @@ void admit(hz_server s) {
 }  // namespace
 
 // ===========================================================================
+// Static device workspace of hz_solve_static
+// ===========================================================================
+namespace {
+
+// One array per GPU the library runs on, held until the process ends.  In host code
+// its name is only a stand-in: kernels receive the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's array, looked up once per device
+char* scratch_address() {
+  int dev = -1;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) fail(HZ_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) fail(HZ_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return static_cast<char*>(g_scratch_ptr[dev]);
+}
+
+// The grid's own binding, set aside while a solve runs on the static workspace and
+// put back afterwards (also when the solve fails).
+struct BindingSwap {
+  hz_grid g;
+  char* ws;
+  int64_t ws_bytes;
+  hipStream_t stream;
+  int prec, cap, last_prec;
+  hz_grid_s::Off off;
+  ShapeTables tab;
+  MaterialTables mtab;
+  std::unique_ptr<Engine> eng;
+  std::vector<Prob> probs;
+  explicit BindingSwap(hz_grid gg)
+      : g(gg), ws(gg->ws), ws_bytes(gg->ws_bytes), stream(gg->stream), prec(gg->prec), cap(gg->cap),
+        last_prec(gg->last_prec), off(gg->off), tab(gg->tab), mtab(gg->mtab), eng(std::move(gg->eng)),
+        probs(std::move(gg->probs)) {}
+  ~BindingSwap() {
+    g->seng = std::move(g->eng);
+    g->eng = std::move(eng);
+    g->probs = std::move(probs);
+    g->ws = ws;
+    g->ws_bytes = ws_bytes;
+    g->stream = stream;
+    g->prec = prec;
+    g->cap = cap;
+    g->last_prec = last_prec;
+    g->off = off;
+    g->tab = tab;
+    g->mtab = mtab;
+  }
+};
+
+}  // namespace
+
+// ===========================================================================
 // C ABI
 // ===========================================================================
 #define HZ_GUARD_BEGIN try {
@@ -556,6 +623,44 @@ int hz_solve(hz_grid g, int32_t n_loads, const double* E, const hz_opts* o, doub
   if (o->scheme == HZ_SCHEME_STRAIN && 2 * n_loads > g->cap)
     fail(HZ_EWORKSPACE, "the strain-based scheme needs a workspace bound for 2 n_loads loads");
   if (o->precision != g->prec) fail(HZ_EWORKSPACE, "workspace bound for another precision");
+  return grid_solve(g, n_loads, E, *o, sigma_mean, eps_out, sig_out, info);
+  HZ_GUARD_END
+}
+
+int hz_solve_static(hz_grid g, void* hip_stream, int32_t n_loads, const double* E, const hz_opts* o,
+                    double* sigma_mean, double* eps_out, double* sig_out, hz_info* info) {
+  HZ_GUARD_BEGIN
+  if (!g || !E || !o || n_loads <= 0) fail(HZ_EINVAL, "bad solve arguments");
+  check_opts(*o);
+  check_loads(E, n_loads);
+  if (!g->mat) fail(HZ_ENOMATERIAL, "material not set");
+  const int nb = o->scheme == HZ_SCHEME_STRAIN ? 2 * n_loads : n_loads;
+  if (nb > 1024) fail(HZ_EINVAL, "at most 1024 loads per handle");
+  hz_grid_s::Off off;
+  grid_layout(g, o->precision, nb, off);
+  if (off.total > kScratchBytes)
+    fail(HZ_EWORKSPACE, "hz_solve_static: the problem needs " + std::to_string(off.total) +
+                            " bytes of workspace; the static workspace holds " + std::to_string(kScratchBytes));
+  char* base = scratch_address();
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  BindingSwap keep(g);
+  if (!g->seng || g->seng->cap < nb) {
+    g->seng.reset();
+    auto e = std::make_unique<Engine>();
+    e->init(nb, false);
+    g->seng = std::move(e);
+  }
+  g->eng = std::move(g->seng);
+  g->eng->prof = &g->prof;
+  g->eng->bind(base + off.engine, st);
+  g->tab = upload_shape_tables(g->shape, base + off.shape_tab, st);
+  g->mtab = upload_material_tables(*g->mat, base + off.mat_tab, st);
+  g->off = off;
+  g->ws = base;
+  g->ws_bytes = (int64_t)kScratchBytes;
+  g->stream = st;
+  g->prec = o->precision;
+  g->cap = nb;
   return grid_solve(g, n_loads, E, *o, sigma_mean, eps_out, sig_out, info);
   HZ_GUARD_END
 }

@@ -796,13 +796,21 @@ size_t Engine::table_bytes(int cap) {
          align_up((size_t)(4 * cap + 16) * 4);
 }
 
-void Engine::init(int c) {
+void Engine::init(int c, bool pinned_mirrors) {
   if (cap) fail(HZ_EINVAL, "executor initialised twice");
   cap = c;
   active_cap = 4 * c + 16;
-  hip_check(hipHostMalloc((void**)&h_desc, (size_t)cap * sizeof(Desc)), "hipHostMalloc");
-  hip_check(hipHostMalloc((void**)&h_status, (size_t)cap * kStatusLen * 8), "hipHostMalloc");
-  hip_check(hipHostMalloc((void**)&h_active, (size_t)active_cap * 4), "hipHostMalloc");
+  pinned = pinned_mirrors;
+  if (pinned) {
+    hip_check(hipHostMalloc((void**)&h_desc, (size_t)cap * sizeof(Desc)), "hipHostMalloc");
+    hip_check(hipHostMalloc((void**)&h_status, (size_t)cap * kStatusLen * 8), "hipHostMalloc");
+    hip_check(hipHostMalloc((void**)&h_active, (size_t)active_cap * 4), "hipHostMalloc");
+  } else {
+    // ordinary host memory: the copies from and to it are staged by the runtime
+    h_desc = new Desc[cap];
+    h_status = new double[(size_t)cap * kStatusLen];
+    h_active = new int[active_cap];
+  }
   std::memset(h_status, 0, (size_t)cap * kStatusLen * 8);
 }
 
@@ -832,9 +840,15 @@ void Engine::start_clock() {
 Engine::~Engine() {
   for (auto ev : evs) (void)hipEventDestroy(ev);
   if (epoch) (void)hipEventDestroy(epoch);
-  if (h_desc) (void)hipHostFree(h_desc);
-  if (h_status) (void)hipHostFree(h_status);
-  if (h_active) (void)hipHostFree(h_active);
+  if (pinned) {
+    if (h_desc) (void)hipHostFree(h_desc);
+    if (h_status) (void)hipHostFree(h_status);
+    if (h_active) (void)hipHostFree(h_active);
+  } else {
+    delete[] h_desc;
+    delete[] h_status;
+    delete[] h_active;
+  }
 }
 
 void Engine::add(Prob* p) {

@@ -222,9 +222,10 @@ struct Engine {
   Desc* d_desc = nullptr;
   double* d_status = nullptr;
   int* d_active = nullptr;
-  Desc* h_desc = nullptr;    // pinned mirrors
-  double* h_status = nullptr;
+  Desc* h_desc = nullptr;    // host mirrors: pinned, or pageable for an engine that must
+  double* h_status = nullptr;  // not call an allocator of the HIP runtime
   int* h_active = nullptr;
+  bool pinned = true;
   int check_every = 8;
   Prof* prof = nullptr;  // owned by the grid or server; never null once bound
   std::vector<Prob*> live;
@@ -233,7 +234,7 @@ struct Engine {
   std::vector<double> ev_ms;
 
   static size_t table_bytes(int cap);
-  void init(int cap);  // pinned mirrors
+  void init(int cap, bool pinned_mirrors = true);
   void bind(char* dev, hipStream_t s);
   void start_clock();
   void add(Prob* p);
