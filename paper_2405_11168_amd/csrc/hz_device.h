@@ -33,9 +33,39 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS, N
   }
 }
 
-__device__ __forceinline__ bool problem_done(const Desc& d) { return d.status[ST_DONE] != 0.0; }
+// A problem's status block as the iteration kernels read it: through the scalar cache
+// (constant address space), since none of them writes it; the stop-rule kernel, which
+// does, reads it through ordinary vector loads.
+#define HZ_CONST __attribute__((address_space(4)))
+__device__ __forceinline__ const HZ_CONST double* status_ro(const Desc& d) {
+  return (const HZ_CONST double*)d.status;
+}
+__device__ __forceinline__ bool problem_done(const Desc& d) { return status_ro(d)[ST_DONE] != 0.0; }
 // ping-pong slot holding the current iterate
-__device__ __forceinline__ int cur_slot(const Desc& d) { return ((int)d.status[ST_K]) & 1; }
+__device__ __forceinline__ int cur_slot(const Desc& d) { return ((int)status_ro(d)[ST_K]) & 1; }
+// the displacement buffer of slot s (a select, so the pointer stays in scalar registers)
+__device__ __forceinline__ void* u_slot(const Desc& d, int s) { return s ? d.u[1] : d.u[0]; }
+
+// Copy a table of n complex values from global memory to LDS: every thread issues all
+// of its loads before its first store, so the table costs one memory latency.
+template <typename T>
+__device__ __forceinline__ void stage_table(cpx<T>* dst, const cpx<T>* __restrict__ src, int n) {
+  constexpr int U = 8;
+#pragma unroll 1
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * kThreads) {
+    cpx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kThreads;
+      if (i < n) v[u] = gld(glb(src) + i);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kThreads;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+}
 
 // D~ (tetrahedron T1) and D~2 (T2) at q from per-axis tables t_a = exp(-i q_a)
 __device__ __forceinline__ void symbols(cpx<double> t1, cpx<double> t2, cpx<double> t3,
@@ -110,7 +140,7 @@ template <typename T>
 __device__ __forceinline__ Mean<T> mean_state(const Desc& d) {
   Mean<T> m;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) m.Eb[c] = uniform((T)d.status[ST_EBAR + c]);
+  for (int c = 0; c < 6; ++c) m.Eb[c] = (T)status_ro(d)[ST_EBAR + c];
   const T* t;
   if constexpr (sizeof(T) == 8) t = reinterpret_cast<const T*>(d.tau64);
   else t = reinterpret_cast<const T*>(d.tau32);

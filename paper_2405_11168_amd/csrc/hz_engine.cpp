@@ -634,11 +634,11 @@ void pass_front(Engine& e, const Shape& sh, const ShapeTables& tb, const int* ac
   const ZGeo zg = zgeo(sh, d);
   {
     Launch L(e, K_ZEXP, d);
-    L.done(launch_zexp<T>(e.d_desc, act, n, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], e.stream), "z expand");
+    L.done(launch_zexp<T>(e.d_desc, act, n, zg, sh.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], e.stream), "z expand");
   }
   const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3, 0};
   Launch L(e, K_YINV, d);
-  L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], true, e.stream), "y inverse");
+  L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], true, e.stream), "y inverse");
 }
 
 // P1 of the strain-based form (apply the previous update to the strains, inverse z)
@@ -651,13 +651,13 @@ void pass_front_strain(Engine& e, const Shape& sh, const ShapeTables& tb, const 
   const ZGeo zg = zgeo(sh, d);
   {
     Launch L(e, K_ZSTRAIN, d);
-    L.done(launch_zstrain<T>(e.d_desc, act, n, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
+    L.done(launch_zstrain<T>(e.d_desc, act, n, zg, sh.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
                              e.stream),
            "z strain");
   }
   const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3, 0};
   Launch L(e, K_YINV, d);
-  L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], true, e.stream), "y inverse");
+  L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], true, e.stream), "y inverse");
 }
 
 // P3: x pass; with fields, T1 writes and T2 then adds its half of the averages.  The
@@ -679,10 +679,10 @@ void pass_x(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, i
       xg.rLRm = recip(M / pi.radix[pi.np - 1]);
       for (int k = 0, off = 0; k < 4; off += cnt[k++])
         if (cnt[k] > 0)
-          L.done(launch_xfused<T>(e.d_desc, act + off, cnt[k], k, xg, tb.plans + 4, tb.plans + 5, tw[0], e.stream),
+          L.done(launch_xfused<T>(e.d_desc, act + off, cnt[k], k, xg, sh.plans + 4, sh.plans + 5, tw[0], e.stream),
                  "x pass");
     } else {
-      L.done(launch_xpass<T>(e.d_desc, act, n, xg, tb.plans + 3, tw[0], e.stream), "x pass");
+      L.done(launch_xpass<T>(e.d_desc, act, n, xg, sh.plans + 3, tw[0], e.stream), "x pass");
     }
   }
 }
@@ -696,12 +696,12 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
   {
     const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3, 0};
     Launch L(e, K_YFWD, d);
-    L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], false, e.stream), "y forward");
+    L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], false, e.stream), "y forward");
   }
   {
     const ZGeo zg = zgeo(sh, d);
     Launch L(e, K_ZCON, d);
-    L.done(launch_zcon<T>(e.d_desc, act, n, false, c0, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
+    L.done(launch_zcon<T>(e.d_desc, act, n, false, c0, zg, sh.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
                           e.stream),
            "z contract");
   }
@@ -741,7 +741,7 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
   {
     const YGeo yg{G.N2, sh.TXy[d], (long long)3 * G.H1 * G.N3, 0, 1};
     Launch L(e, K_YINV3, d);
-    L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], true, e.stream), "y inverse");
+    L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], true, e.stream), "y inverse");
   }
   const int M = G.N1 / 2;
   XGeo xg{G.N1, G.N2, G.N3, G.H1, sh.H1p[d], sh.TY3[d], M, recip(sh.TY3[d]), recip(M / 2 + 1), recip(M),
@@ -750,7 +750,7 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
     const Plan& pi = sh.plans[6];
     xg.rNI = recip(M / pi.radix[0] / 2 + 1);
     Launch L(e, K_XC2R, d);
-    L.done(launch_xc2r<T>(e.d_desc, act, n, xg, tb.plans + 6, pi.radix[0], tw[0], e.stream), "x c2r");
+    L.done(launch_xc2r<T>(e.d_desc, act, n, xg, sh.plans + 6, pi.radix[0], tw[0], e.stream), "x c2r");
   }
   {
     Launch L(e, K_STEN, d);
@@ -761,16 +761,16 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
     const Plan& pf = sh.plans[7];
     xg.rNI = recip(M / pf.radix[pf.np - 1] / 2 + 1);
     Launch L(e, K_XR2C, d);
-    L.done(launch_xr2c<T>(e.d_desc, act, n, xg, tb.plans + 7, pf.radix[pf.np - 1], tw[0], e.stream), "x r2c");
+    L.done(launch_xr2c<T>(e.d_desc, act, n, xg, sh.plans + 7, pf.radix[pf.np - 1], tw[0], e.stream), "x r2c");
   }
   {
     const YGeo yg{G.N2, sh.TXy[d], (long long)3 * G.H1 * G.N3, 9 * G.S};
     Launch L(e, K_YFWD3, d);
-    L.done(launch_yline<T>(e.d_desc, act, n, yg, tb.plans + 1, tw[1], false, e.stream), "y forward");
+    L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], false, e.stream), "y forward");
   }
   {
     Launch L(e, K_ZCON3, d);
-    L.done(launch_zcon<T>(e.d_desc, act, n, true, c0, zg, tb.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
+    L.done(launch_zcon<T>(e.d_desc, act, n, true, c0, zg, sh.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
                           e.stream),
            "z contract");
   }
@@ -862,7 +862,7 @@ void Engine::add(Prob* p) {
 
 void Engine::convert_stencil_state(void* u, const Prob& p, bool inverse) {
   Launch L(*this, K_ZCONV3, 1);
-  L.done(launch_zconv3(u, inverse, zgeo(*p.shape, 1), p.tab.plans + 2, p.tab.tw64[2], stream), "z convert");
+  L.done(launch_zconv3(u, inverse, zgeo(*p.shape, 1), p.shape->plans + 2, p.tab.tw64[2], stream), "z convert");
 }
 
 void Engine::enter_state(Prob* p) {

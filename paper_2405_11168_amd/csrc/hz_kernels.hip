@@ -43,9 +43,11 @@ namespace hz {
 // ----------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ descs, const int* __restrict__ active,
-                                                   ZGeo zg, const Plan* __restrict__ plan3, const cpx<T>* __restrict__ tw3T,
+                                                   ZGeo zg, const Plan plan3v, const cpx<T>* __restrict__ tw3T,
                                                    const cpx<double>* __restrict__ tw1,
                                                    const cpx<double>* __restrict__ tw2) {
+  const Plan* plan3 = &plan3v;  // kernel argument (scalar loads)
+
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
@@ -56,10 +58,10 @@ __global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ desc
   const int lines = 3 * TX;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* twl = buf + lines * N3;
-  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
+  stage_table(twl, tw3T, N3);
   const long long plane = (long long)h1 * N3 * N2 + h2_0;
   const LdsAcc<T> lds{buf, 1, lines};
-  const void* usrc = d.src == 1 ? d.u64 : d.u[cur_slot(d)];
+  const void* usrc = d.src == 1 ? d.u64 : u_slot(d, cur_slot(d));
   const GblAcc<T> src{glb(reinterpret_cast<cpx<T>*>(const_cast<void*>(usrc))) + plane, (int)zg.S, TX, 1, N2};
   fft_lines<T, emax<T>(), true>(*plan3, lines, zg.rLines, false, twl, 1, lds, src, lds);
   __syncthreads();
@@ -113,11 +115,13 @@ __global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ desc
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_zstrain(const Desc* __restrict__ descs,
                                                       const int* __restrict__ active, ZGeo zg,
-                                                      const Plan* __restrict__ plan3,
+                                                      const Plan plan3v,
                                                       const cpx<T>* __restrict__ tw3T,
                                                       const cpx<double>* __restrict__ tw1,
                                                       const cpx<double>* __restrict__ tw2,
                                                       const cpx<double>* __restrict__ tw3) {
+  const Plan* plan3 = &plan3v;  // kernel argument (scalar loads)
+
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
@@ -128,9 +132,9 @@ __global__ __launch_bounds__(kThreads) void k_zstrain(const Desc* __restrict__ d
   const int lines = 3 * TX;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* twl = buf + lines * N3;
-  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
+  stage_table(twl, tw3T, N3);
   const bool iter = d.cmode == 3;
-  const int k = (int)d.status[ST_K];
+  const int k = (int)status_ro(d)[ST_K];
   const bool fresh = iter && k == 0, apply = iter && k > 0;
   const long long plane = (long long)h1 * N3 * N2 + h2_0;
   HZ_GLB cpx<T>* st = glb(reinterpret_cast<cpx<T>*>(d.state)) + plane;
@@ -184,7 +188,9 @@ __global__ __launch_bounds__(kThreads) void k_zstrain(const Desc* __restrict__ d
 // ----------------------------------------------------------------------------
 template <typename T, bool INV>
 __global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ descs, const int* __restrict__ active,
-                                                    YGeo yg, const Plan* __restrict__ plan2, const cpx<T>* __restrict__ tw2T) {
+                                                    YGeo yg, const Plan plan2v, const cpx<T>* __restrict__ tw2T) {
+  const Plan* plan2 = &plan2v;  // kernel argument (scalar loads)
+
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
@@ -193,11 +199,11 @@ __global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ des
   const int lines = (int)((yg.nlines - t0) < yg.TX ? (yg.nlines - t0) : yg.TX);
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* twl = buf + yg.TX * N2;
-  for (int i = threadIdx.x; i < N2; i += kThreads) twl[i] = tw2T[i];
+  stage_table(twl, tw2T, N2);
   const LdsAcc<T> lds{buf, N2, 1};
   const GblAcc<T> g{glb(reinterpret_cast<cpx<T>*>(d.spec)) + yg.off + t0 * N2, N2, 1, 0, 1};
   if (yg.from_state) {
-    void* st = d.src == 1 ? d.u64 : d.u[cur_slot(d)];
+    void* st = d.src == 1 ? d.u64 : u_slot(d, cur_slot(d));
     const GblAcc<T> src{glb(reinterpret_cast<cpx<T>*>(st)) + t0 * N2, N2, 1, 0, 1};
     fft_lines<T, emax<T>(), INV>(*plan2, lines, 0.f, true, twl, 1, lds, src, g);
   } else {
@@ -214,7 +220,9 @@ __global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ des
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ descs,
                                                     const int* __restrict__ active, XGeo xg,
-                                                    const Plan* __restrict__ planM, const cpx<T>* __restrict__ twN1) {
+                                                    const Plan planMv, const cpx<T>* __restrict__ twN1) {
+  const Plan* planM = &planMv;  // kernel argument (scalar loads)
+
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[6 * 4];
   const Desc& d = descs[active[blockIdx.y]];
@@ -233,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
   const HZ_GLB uint16_t* ph = glb(d.phase) + ((long long)l3 * xg.N2 + l2_0) * xg.N1;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);  // 6*TY lines of M (pitch H1p)
   cpx<T>* twl = buf + 6 * TY * H1p;
-  for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
+  stage_table(twl, twN1, xg.N1);
   const int kh = M / 2 + 1;             // (k, M-k) pairs per line, k = 0..M/2
   const int npair = 6 * kh * TY;
   const LdsAcc<T> lds{buf, H1p, 1};
@@ -363,9 +371,12 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const Desc* __restrict__ des
 template <typename T, bool ISO, bool EIG>
 __global__ __launch_bounds__(kThreads) void k_xfused(const Desc* __restrict__ descs,
                                                      const int* __restrict__ active, XGeo xg,
-                                                     const Plan* __restrict__ planXi,
-                                                     const Plan* __restrict__ planXf,
+                                                     const Plan planXiv,
+                                                     const Plan planXfv,
                                                      const cpx<T>* __restrict__ twN1) {
+  const Plan* planXi = &planXiv;  // kernel argument (scalar loads)
+  const Plan* planXf = &planXfv;  // kernel argument (scalar loads)
+
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[6 * 4];
   const Desc& d = descs[active[blockIdx.y]];
@@ -380,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_xfused(const Desc* __restrict__ de
   const long long row0 = (long long)l3 * xg.N2 + l2_0;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* twl = buf + 6 * TY * xg.H1p;
-  for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
+  stage_table(twl, twN1, xg.N1);
   __syncthreads();
   const int off = (int)(half * 6 * xg.S + row0);
   const HZ_GLB cpx<T>* src = glb(reinterpret_cast<const cpx<T>*>(d.spec)) + off;
@@ -440,7 +451,7 @@ hipError_t launch_zexp(const Desc* descs, const int* active, int nact, const ZGe
                        const void* tw3T, const void* tw1, const void* tw2, hipStream_t s) {
   const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
   dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
-  hipLaunchKernelGGL(k_zexp<T>, grid, dim3(kThreads), shm, s, descs, active, zg, plan3, (const cpx<T>*)tw3T,
+  hipLaunchKernelGGL(k_zexp<T>, grid, dim3(kThreads), shm, s, descs, active, zg, *plan3, (const cpx<T>*)tw3T,
                      (const cpx<double>*)tw1, (const cpx<double>*)tw2);
   return hipGetLastError();
 }
@@ -451,9 +462,9 @@ hipError_t launch_yline(const Desc* descs, const int* active, int nact, const YG
   const size_t shm = ((size_t)yg.TX * yg.N2 + yg.N2) * sizeof(cpx<T>);
   dim3 grid((unsigned)((yg.nlines + yg.TX - 1) / yg.TX), nact);
   if (inv)
-    hipLaunchKernelGGL((k_yline<T, true>), grid, dim3(kThreads), shm, s, descs, active, yg, plan2, (const cpx<T>*)tw2T);
+    hipLaunchKernelGGL((k_yline<T, true>), grid, dim3(kThreads), shm, s, descs, active, yg, *plan2, (const cpx<T>*)tw2T);
   else
-    hipLaunchKernelGGL((k_yline<T, false>), grid, dim3(kThreads), shm, s, descs, active, yg, plan2, (const cpx<T>*)tw2T);
+    hipLaunchKernelGGL((k_yline<T, false>), grid, dim3(kThreads), shm, s, descs, active, yg, *plan2, (const cpx<T>*)tw2T);
   return hipGetLastError();
 }
 
@@ -462,7 +473,7 @@ hipError_t launch_xpass(const Desc* descs, const int* active, int nact, const XG
                         const Plan* planM, const void* twN1, hipStream_t s) {
   const size_t shm = ((size_t)6 * xg.TY * xg.H1p + xg.N1) * sizeof(cpx<T>);
   dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY) * (xg.half >= 0 ? 1 : 2)), nact);
-  hipLaunchKernelGGL(k_xpass<T>, grid, dim3(kThreads), shm, s, descs, active, xg, planM,
+  hipLaunchKernelGGL(k_xpass<T>, grid, dim3(kThreads), shm, s, descs, active, xg, *planM,
                      (const cpx<T>*)twN1);
   return hipGetLastError();
 }
@@ -475,16 +486,16 @@ hipError_t launch_xfused(const Desc* descs, const int* active, int nact, int kin
   const cpx<T>* tw = (const cpx<T>*)twN1;
   switch (kind) {
     case KIND_ISO:
-      hipLaunchKernelGGL((k_xfused<T, true, false>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf, tw);
+      hipLaunchKernelGGL((k_xfused<T, true, false>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, *planXf, tw);
       break;
     case KIND_ISO | KIND_EIG:
-      hipLaunchKernelGGL((k_xfused<T, true, true>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf, tw);
+      hipLaunchKernelGGL((k_xfused<T, true, true>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, *planXf, tw);
       break;
     case 0:
-      hipLaunchKernelGGL((k_xfused<T, false, false>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf, tw);
+      hipLaunchKernelGGL((k_xfused<T, false, false>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, *planXf, tw);
       break;
     default:
-      hipLaunchKernelGGL((k_xfused<T, false, true>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, planXf, tw);
+      hipLaunchKernelGGL((k_xfused<T, false, true>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, *planXf, tw);
       break;
   }
   return hipGetLastError();
@@ -495,7 +506,7 @@ hipError_t launch_zstrain(const Desc* descs, const int* active, int nact, const 
                           const void* tw3T, const void* tw1, const void* tw2, const void* tw3, hipStream_t s) {
   const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
   dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
-  hipLaunchKernelGGL(k_zstrain<T>, grid, dim3(kThreads), shm, s, descs, active, zg, plan3, (const cpx<T>*)tw3T,
+  hipLaunchKernelGGL(k_zstrain<T>, grid, dim3(kThreads), shm, s, descs, active, zg, *plan3, (const cpx<T>*)tw3T,
                      (const cpx<double>*)tw1, (const cpx<double>*)tw2, (const cpx<double>*)tw3);
   return hipGetLastError();
 }

@@ -24,8 +24,10 @@ namespace hz {
 // scaled by 1/N3 (a finished problem's reported iterate).
 template <bool INV>
 __global__ __launch_bounds__(kThreads) void k_zconv3(cpx<double>* __restrict__ u, ZGeo zg,
-                                                     const Plan* __restrict__ plan3,
+                                                     const Plan plan3v,
                                                      const cpx<double>* __restrict__ tw3, double scale) {
+  const Plan* plan3 = &plan3v;  // kernel argument (scalar loads)
+
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int TX = zg.TX, N2 = zg.N2, N3 = zg.N3;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(kThreads) void k_zconv3(cpx<double>* __restrict__ u
   const int lines = 3 * TX;
   cpx<double>* buf = reinterpret_cast<cpx<double>*>(smem_raw);
   cpx<double>* twl = buf + lines * N3;
-  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3[i];
+  stage_table(twl, tw3, N3);
   __syncthreads();
   const LdsAcc<double> lds{buf, 1, lines};
   const GblAcc<double> g{glb(u) + (long long)h1 * N3 * N2 + h2_0, (int)zg.S, TX, 1, N2};
@@ -58,8 +60,10 @@ __global__ __launch_bounds__(kThreads) void k_zconv3(cpx<double>* __restrict__ u
 // of the radix actually used)
 template <typename T, int R0>
 __global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ descs, const int* __restrict__ active,
-                                                   XGeo xg, const Plan* __restrict__ planXi,
+                                                   XGeo xg, const Plan planXiv,
                                                    const cpx<T>* __restrict__ twN1) {
+  const Plan* planXi = &planXiv;  // kernel argument (scalar loads)
+
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ desc
   const int row0 = l3 * xg.N2 + l2_0;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* twl = buf + 3 * TY * xg.H1p;
-  for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
+  stage_table(twl, twN1, xg.N1);
   __syncthreads();
   HZ_GLB cpx<T>* spec = glb(reinterpret_cast<cpx<T>*>(d.spec));
   const Plan& pi = *planXi;
@@ -97,8 +101,10 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ desc
 // RL: the plan's last radix (the merge pass).
 template <typename T, int RL>
 __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ descs, const int* __restrict__ active,
-                                                   XGeo xg, const Plan* __restrict__ planXf,
+                                                   XGeo xg, const Plan planXfv,
                                                    const cpx<T>* __restrict__ twN1) {
+  const Plan* planXf = &planXfv;  // kernel argument (scalar loads)
+
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d)) return;
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ desc
   const int row0 = l3 * xg.N2 + l2_0;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* twl = buf + 3 * TY * xg.H1p;
-  for (int i = threadIdx.x; i < xg.N1; i += kThreads) twl[i] = twN1[i];
+  stage_table(twl, twN1, xg.N1);
   __syncthreads();
   HZ_GLB cpx<T>* spec = glb(reinterpret_cast<cpx<T>*>(d.spec));
   const Plan& pf = *planXf;
@@ -433,8 +439,8 @@ hipError_t launch_zconv3(void* u, bool inverse, const ZGeo& zg, const Plan* plan
   const dim3 grid((unsigned)(zg.H1 * zg.tiles));
   cpx<double>* p = reinterpret_cast<cpx<double>*>(u);
   const cpx<double>* tw = (const cpx<double>*)tw3;
-  if (inverse) hipLaunchKernelGGL(k_zconv3<true>, grid, dim3(kThreads), shm, s, p, zg, plan3, tw, 1.0);
-  else hipLaunchKernelGGL(k_zconv3<false>, grid, dim3(kThreads), shm, s, p, zg, plan3, tw, 1.0 / zg.N3);
+  if (inverse) hipLaunchKernelGGL(k_zconv3<true>, grid, dim3(kThreads), shm, s, p, zg, *plan3, tw, 1.0);
+  else hipLaunchKernelGGL(k_zconv3<false>, grid, dim3(kThreads), shm, s, p, zg, *plan3, tw, 1.0 / zg.N3);
   return hipGetLastError();
 }
 
@@ -445,10 +451,10 @@ hipError_t launch_xc2r(const Desc* descs, const int* active, int nact, const XGe
   dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY)), nact);
   const cpx<T>* tw = (const cpx<T>*)twN1;
   switch (r0) {
-    case 16: hipLaunchKernelGGL((k_xc2r<T, 16>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, tw); break;
-    case 8: hipLaunchKernelGGL((k_xc2r<T, 8>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, tw); break;
-    case 4: hipLaunchKernelGGL((k_xc2r<T, 4>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, tw); break;
-    case 2: hipLaunchKernelGGL((k_xc2r<T, 2>), grid, dim3(kThreads), shm, s, descs, active, xg, planXi, tw); break;
+    case 16: hipLaunchKernelGGL((k_xc2r<T, 16>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
+    case 8: hipLaunchKernelGGL((k_xc2r<T, 8>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
+    case 4: hipLaunchKernelGGL((k_xc2r<T, 4>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
+    case 2: hipLaunchKernelGGL((k_xc2r<T, 2>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -461,10 +467,10 @@ hipError_t launch_xr2c(const Desc* descs, const int* active, int nact, const XGe
   dim3 grid((unsigned)(xg.N3 * (xg.N2 / xg.TY)), nact);
   const cpx<T>* tw = (const cpx<T>*)twN1;
   switch (rl) {
-    case 16: hipLaunchKernelGGL((k_xr2c<T, 16>), grid, dim3(kThreads), shm, s, descs, active, xg, planXf, tw); break;
-    case 8: hipLaunchKernelGGL((k_xr2c<T, 8>), grid, dim3(kThreads), shm, s, descs, active, xg, planXf, tw); break;
-    case 4: hipLaunchKernelGGL((k_xr2c<T, 4>), grid, dim3(kThreads), shm, s, descs, active, xg, planXf, tw); break;
-    case 2: hipLaunchKernelGGL((k_xr2c<T, 2>), grid, dim3(kThreads), shm, s, descs, active, xg, planXf, tw); break;
+    case 16: hipLaunchKernelGGL((k_xr2c<T, 16>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
+    case 8: hipLaunchKernelGGL((k_xr2c<T, 8>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
+    case 4: hipLaunchKernelGGL((k_xr2c<T, 4>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
+    case 2: hipLaunchKernelGGL((k_xr2c<T, 2>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

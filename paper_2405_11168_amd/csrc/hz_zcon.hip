@@ -32,10 +32,12 @@ __device__ __forceinline__ void sig_dot(const cpx<T> (&s)[6], const cpx<double>*
 // block); the generic variant contracts the full lambda0 tensor.
 template <typename T, bool STENCIL, bool C0ISO>
 __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ descs, const int* __restrict__ active,
-                                                   ZGeo zg, const Plan* __restrict__ plan3, const cpx<T>* __restrict__ tw3T,
+                                                   ZGeo zg, const Plan plan3v, const cpx<T>* __restrict__ tw3T,
                                                    const cpx<double>* __restrict__ tw1,
                                                    const cpx<double>* __restrict__ tw2,
                                                    const cpx<double>* __restrict__ tw3) {
+  const Plan* plan3 = &plan3v;  // kernel argument (scalar loads)
+
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[4];
   const Desc& d = descs[active[blockIdx.y]];
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
   const int lines = 3 * TX;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* twl = buf + lines * N3;
-  for (int i = threadIdx.x; i < N3; i += kThreads) twl[i] = tw3T[i];
+  stage_table(twl, tw3T, N3);
   const long long plane = (long long)h1 * N3 * N2 + h2_0;
   const LdsAcc<T> lds{buf, 1, lines};
   const HZ_GLB cpx<T>* sp = glb(reinterpret_cast<const cpx<T>*>(d.spec)) + plane;
@@ -124,8 +126,8 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
   const double w = (h1 == 0 || 2 * h1 == zg.N1) ? 1.0 : 2.0;
   const int MODE = d.cmode;
   const int p = cur_slot(d);
-  const HZ_GLB cpx<T>* uin = glb(reinterpret_cast<const cpx<T>*>(d.u[p])) + plane;
-  HZ_GLB cpx<T>* uout = glb(reinterpret_cast<cpx<T>*>(d.u[MODE == 3 ? 0 : 1 - p])) + plane;
+  const HZ_GLB cpx<T>* uin = glb(reinterpret_cast<const cpx<T>*>(u_slot(d, p))) + plane;
+  HZ_GLB cpx<T>* uout = glb(reinterpret_cast<cpx<T>*>(u_slot(d, MODE == 3 ? 0 : 1 - p))) + plane;
   const HZ_GLB cpx<float>* r32in = glb(reinterpret_cast<const cpx<float>*>(d.r32)) + plane;
   HZ_GLB cpx<float>* r32out = glb(reinterpret_cast<cpx<float>*>(d.r32)) + plane;
   constexpr int CH = 4;
@@ -396,8 +398,8 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const Desc* __restrict_
   const Desc& d = descs[active[blockIdx.y]];
   const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
   if (idx >= n3c) return;
-  const int p = (int)d.status[ST_PARITY];
-  const cpx<float> a = ld<float>(d.u[p], idx);
+  const int p = (int)status_ro(d)[ST_PARITY];
+  const cpx<float> a = ld<float>(u_slot(d, p), idx);
   cpx<double> b = ld<double>(d.u64, idx);
   b.x += (double)a.x;
   b.y += (double)a.y;
@@ -423,7 +425,7 @@ void launch_zcon1(const Desc* descs, const int* active, int nact, const ZGeo& zg
                   const void* tw3T, const void* tw1, const void* tw2, const void* tw3, hipStream_t s) {
   const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
   dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
-  hipLaunchKernelGGL((k_zcon<T, STENCIL, C0ISO>), grid, dim3(kThreads), shm, s, descs, active, zg, plan3,
+  hipLaunchKernelGGL((k_zcon<T, STENCIL, C0ISO>), grid, dim3(kThreads), shm, s, descs, active, zg, *plan3,
                      (const cpx<T>*)tw3T, (const cpx<double>*)tw1, (const cpx<double>*)tw2, (const cpx<double>*)tw3);
 }
 

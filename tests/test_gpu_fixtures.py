@@ -52,8 +52,7 @@ def _problem(fx):
 
 def _load(name):
     path = os.path.join(HERE, "golden", name + ".json")
-    if not os.path.exists(path):
-        pytest.skip(f"fixture {path} not generated yet: run tests/golden/make_fixtures.py {name}")
+    assert os.path.exists(path), f"missing fixture {path}: run tests/golden/make_fixtures.py {name}"
     with open(path) as f:
         return json.load(f)
 

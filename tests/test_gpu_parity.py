@@ -100,6 +100,13 @@ def check_pair(shape, g, r, ref, K, fields=True):
     ((16, 256, 8), 2, 10, "iso", False, 2),      # radix 16 x 16 along y
     ((16, 8, 256), 2, 11, "iso", False, 2),      # radix 16 x 16 along z
     ((96, 48, 40), 2, 12, "aniso", True, 3),     # radix 3 and 5 at medium size, voids
+    # N1 a multiple of 64 with few rows and planes: ragged stencil tiles along y, z segments
+    # shorter than a tile, three-pass x transforms
+    ((64, 12, 10), 2, 13, "iso", False, 3),
+    ((128, 20, 6), 3, 14, "aniso", True, 3),
+    ((192, 14, 4), 2, 15, "iso", True, 2),
+    ((64, 4, 2), 2, 16, "aniso", False, 3),
+    ((320, 6, 4), 2, 17, "iso", False, 2),
 ])
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
 def test_fp64_iterates_match_oracle(shape, n_phases, seed, kind, voids, K, scheme):
@@ -241,6 +248,22 @@ def test_fp32_refine_ceff_within_1e6_of_converged_oracle(scheme):
     err = np.abs(Ce - Co).max() / np.abs(Co).max()
     _say(f"  refine C_eff rel err {err:.2e}")
     assert err < 1e-6
+
+
+def test_fp32_refine_stencil_form_matches_converged_oracle():
+    """FP32+refine in the stencil form on a grid with several stencil tiles per row and
+    plane (FP32 iterations and FP64 sweeps): <sigma> within 1e-6 of the converged oracle,
+    for an isotropic and an anisotropic material."""
+    for seed, kind in ((41, "iso"), (42, "aniso")):
+        ph, C, C0, E = random_problem((64, 16, 12), 2, seed, kind)
+        g = hz.Grid(64, 16, 12)
+        g.set_material(C, ph)
+        r = g.solve(E, tol=1e-9, C0=C0, precision=hz.HZ_FP32_REFINE, scheme=hz.HZ_SCHEME_STENCIL)
+        ref = tetra.basic_scheme(ph, C, C0, E[0], tol=1e-12, keep_fields=False)
+        err = np.abs(r.mean_sigma[0] - ref.mean_sigma).max() / np.abs(ref.mean_sigma).max()
+        _say(f"  refine stencil form {kind}: status {r.status[0]} iters {r.iters[0]} rounds {r.outer_rounds[0]} "
+             f"<sigma> vs converged {err:.1e}")
+        assert r.status[0] == hz.HZ_OK and err < 1e-6
 
 
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
