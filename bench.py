@@ -18,14 +18,25 @@ Prints ONE JSON line:
                  kernel's launches only), against 8 TB/s
   per_kernel     mean launch durations from an untimed run with events around every
                  launch (it also picks the dominant kernel)
-  cpu_baseline   the CPU oracle timed on the host on a bounded sample
+  iteration_roofline_frac  the whole iteration's algorithmic bytes per voxel-iteration
+                 x value / 8 TB/s
+  ceff_converged the same workload run to eps < 1e-8 (FP64, and FP32+refine beside it):
+                 C_eff, iterations and status per load, symmetry residual, the margins to
+                 the Voigt and Reuss bounds
+  full_size      FP64 fixed-iteration throughput and whole-iteration roofline fraction of
+                 the 256^3 Voronoi polycrystal and of the 192x192x320 Boolean spheres (6
+                 loads each), with per-kernel rates, and the FP32 iteration (fixed FP32
+                 count) on the same workloads
+  cpu_baseline   the CPU oracle timed on the host on a bounded sample (CPU model stated)
   time_to_1e-6   FP32+refinement vs plain FP64 device time to an FP64-verified
-                 residual of 1e-6 on the 256^3 Voronoi polycrystal (6 loads)
+                 residual of 1e-6 on the 256^3 Voronoi polycrystal (6 loads); the speedup
+                 only when every load of both solves converged
   serving        a seeded stream of solve requests (grid sizes 32..192^3, Boolean
                  spheres or cubic polycrystals, contrast log-uniform 1e1..1e6, one
                  load each, FP32+refine to 1e-6) through the solve server: closed-loop
                  saturation throughput, then Poisson arrivals at 0.7x that rate with
-                 p50/p99 latency from arrival to result
+                 p50/p99 latency from arrival to result over the requests that reached
+                 1e-6, the count of those that did not beside them
 """
 import argparse
 import hashlib
@@ -89,6 +100,24 @@ def iteration_bytes(scheme, S, N, csz):
     return sum(kernel_bytes(k, S, N, 1, csz) for k in kinds)
 
 
+def host_cpu():
+    """CPU model name and the logical CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
 def cpu_baseline(problem, max_seconds=15.0):
     """The oracle (FP64 numpy/scipy, Algorithm 1) on a bounded sample: one load,
     a few iterations of the same 128^3 workload, timed on the host."""
@@ -107,20 +136,21 @@ def cpu_baseline(problem, max_seconds=15.0):
                            keep_fields=False)
         dt = time.perf_counter() - t0
         iters = k
+    model, avail = host_cpu()
     return {"value": n * iters / dt, "unit": "voxel-iters/s", "cores": tetra.WORKERS, "kind": "oracle",
-            "sample": f"1 of 6 loads, {iters} iteration(s) of the 128^3 workload (FP64 numpy+scipy.fft), "
-                      f"{dt:.1f} s wall"}
+            "cpu_model": model, "cpus_available": avail,
+            "sample": f"1 of 6 loads, {iters} iteration(s) of the 128^3 workload (FP64 numpy+scipy.fft, "
+                      f"{tetra.WORKERS} FFT threads), {dt:.1f} s wall"}
 
 
-def time_to_tol(syn, hz, np, torch, n):
+def time_to_tol(hz, np, torch, p, g):
     """Device time to an FP64-verified residual of 1e-6 on the periodic Voronoi
     polycrystal (200 cubic grains C11=168, C12=121, C44=75, random orientations,
     6 unit loads): plain FP64 iterations against FP32 iterations anchored by FP64
     sweeps.  Each variant runs three times: a warmup, a run with HIP events around
-    every launch (per-kernel times), and the reported run without them."""
-    p = syn.polycrystal(shape=(n, n, n))
-    g = hz.Grid(*p.shape)
-    g.set_material(p.C, p.phase)
+    every launch (per-kernel times), and the reported run without them.  The speedup
+    is reported only when every load of both solves converged."""
+    n = p.shape[0]
     out = {"workload": f"voronoi{n}_200grains_cubic_6loads", "tol": 1e-6}
     res = {}
     for prec, name in ((hz.HZ_FP64, "fp64"), (hz.HZ_FP32_REFINE, "fp32_refine")):
@@ -136,14 +166,114 @@ def time_to_tol(syn, hz, np, torch, n):
                 prof = g.profile_read()
         g.profile(False)
         res[name] = r
-        out[name] = {"seconds_to_1e-6": round(float(np.max(r.seconds_to_1e6)), 4), "wall_s": round(wall, 4),
-                     "iters": int(np.max(r.iters)), "outer_rounds": int(np.max(r.outer_rounds)),
-                     "residual": float(np.max(r.residual)),
+        ok = bool(np.all(r.status == hz.HZ_OK) and np.all(r.seconds_to_1e6 > 0))
+        out[name] = {"all_converged": ok, "status": [int(x) for x in r.status],
+                     "seconds_to_1e-6": round(float(np.max(r.seconds_to_1e6)), 4) if ok else None,
+                     "wall_s": round(wall, 4), "iters": [int(x) for x in r.iters],
+                     "outer_rounds": [int(x) for x in r.outer_rounds], "residual": float(np.max(r.residual)),
                      "kernel_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in prof.items()}}
-    out["speedup"] = round(out["fp64"]["seconds_to_1e-6"] / out["fp32_refine"]["seconds_to_1e-6"], 3)
+    both = out["fp64"]["all_converged"] and out["fp32_refine"]["all_converged"]
+    out["speedup"] = (round(out["fp64"]["seconds_to_1e-6"] / out["fp32_refine"]["seconds_to_1e-6"], 3)
+                      if both else None)
     m64, m32 = res["fp64"].mean_sigma, res["fp32_refine"].mean_sigma
     out["ceff_rel_diff_fp32r_vs_fp64"] = float(np.abs(m32 - m64).max() / np.abs(m64).max())
-    del g
+    return out
+
+
+def kernel_rates(prof, S, N, nloads):
+    """Per kernel of a profiled run: mean ms per launch and, where the kernel has an
+    algorithmic byte count (launches over all `nloads` loads; the stencil-state
+    conversion runs per load), its achieved GB/s and fraction of 8 TB/s."""
+    out = {}
+    for name, (ms, cnt) in sorted(prof.items()):
+        kind, prec = name.rsplit("_", 1)
+        b = kernel_bytes(kind, S, N, 1 if kind == "zconvert3" else nloads, 16 if prec == "f64" else 8)
+        t = ms / cnt
+        e = {"ms_per_launch": round(t, 4), "launches": cnt}
+        if b is not None:
+            gbs = b / (t * 1e-3) / 1e9
+            e.update({"GB_per_launch": round(b / 1e9, 4), "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        out[name] = e
+    return out
+
+
+def full_size_leg(hz, np, torch, name, p, g, loads, K1=4, K2=24):
+    """Iteration rate of `loads` on one full-size grid, FP64 and FP32, from two runs of
+    fixed length: (t(K2) - t(K1)) / (K2 - K1) per iteration, so the solve's set-up and
+    its final measurement cancel.  FP32: a fixed FP32 count (K FP32 updates, one FP64
+    sweep).  A third, profiled run of K2 gives the per-kernel rates."""
+    N1, N2, N3 = p.shape
+    N = N1 * N2 * N3
+    S = (N1 // 2 + 1) * N2 * N3
+    nl = len(loads)
+    out = {"workload": name, "grid": [N1, N2, N3], "loads": nl, "passes_timed": K2 - K1}
+    for prec, key, csz in ((hz.HZ_FP64, "fp64", 16), (hz.HZ_FP32_REFINE, "fp32", 8)):
+        g.bind(prec, nl)
+
+        def run(K):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = g.solve(loads, C0=p.C0, precision=prec, fixed_iters=K, check_every=1 << 20)
+            torch.cuda.synchronize()
+            assert np.all(r.iters == K), r.iters
+            return time.perf_counter() - t0
+
+        run(2)
+        t1, t2 = run(K1), run(K2)
+        g.profile(True)
+        run(K2)
+        torch.cuda.synchronize()
+        g.profile(False)
+        prof = g.profile_read()
+        per_iter = (t2 - t1) / (K2 - K1)
+        scheme = "stencil" if any(k.startswith("stencil") for k in prof) else "spectral"
+        bpv = iteration_bytes(scheme, S, N, csz) / N
+        vips = N * nl / per_iter
+        out[key] = {"ms_per_iteration": round(per_iter * 1e3, 4), "voxel_iters_per_s": vips, "scheme": scheme,
+                    "bytes_per_voxel_iteration": round(bpv, 1),
+                    "iteration_roofline_frac": round(vips * bpv / (HBM_PEAK_GBS * 1e9), 4),
+                    "kernels": {k: v for k, v in kernel_rates(prof, S, N, nl).items()
+                                if k.endswith("f64" if key == "fp64" else "f32")}}
+    return out
+
+
+def bounds_margins(np, Ce, C, phase):
+    """Symmetry residual of C_eff and its margins to the Voigt bound (volume average of
+    the stiffnesses) and the Reuss bound (inverse of the average compliance): the
+    smallest eigenvalue of C_V - C_eff and of C_eff - C_R in Mandel form (shear rows and
+    columns of the engineering-shear Voigt matrix scaled by sqrt 2), relative to the largest eigenvalue of C_eff; both are
+    >= 0 for an admissible result."""
+    f = np.bincount(phase.ravel(), minlength=len(C)) / phase.size
+    CV = np.einsum("p,pij->ij", f, C)
+    CR = np.linalg.inv(np.einsum("p,pij->ij", f, np.linalg.inv(C)))
+    W = np.diag(np.array([1, 1, 1, 2 ** .5, 2 ** .5, 2 ** .5]))  # Mandel = W C W for engineering-shear Voigt
+    sym = 0.5 * (Ce + Ce.T)
+    top = np.linalg.eigvalsh(W @ sym @ W).max()
+    return {"symmetry_residual": float(np.abs(Ce - Ce.T).max() / np.abs(Ce).max()),
+            "voigt_margin": float(np.linalg.eigvalsh(W @ (CV - sym) @ W).min() / top),
+            "reuss_margin": float(np.linalg.eigvalsh(W @ (sym - CR) @ W).min() / top)}
+
+
+def ceff_leg(hz, np, torch, p, g, tol=1e-8, max_iters=200000):
+    """C_eff of the headline workload run to convergence: the six unit loads as one
+    batch (hz_effective_stiffness), FP64 and FP32+refine."""
+    out = {"workload": "boolean128_contrast1e3_6loads", "tol": tol, "max_iters": max_iters}
+    res = {}
+    for prec, key in ((hz.HZ_FP64, "fp64"), (hz.HZ_FP32_REFINE, "fp32_refine")):
+        g.bind(prec, 6)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Ce, r = g.effective_stiffness(tol=tol, max_iters=max_iters, precision=prec, C0=p.C0, check_every=64)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[key] = Ce
+        out[key] = {"all_converged": bool(np.all(r.status == hz.HZ_OK)), "status": [int(x) for x in r.status],
+                    "iters": [int(x) for x in r.iters], "outer_rounds": [int(x) for x in r.outer_rounds],
+                    "residual": [float(x) for x in r.residual], "device_s": round(float(np.max(r.seconds)), 3),
+                    "wall_s": round(wall, 3), "C_eff": [[float(f"{x:.9g}") for x in row] for row in Ce],
+                    **bounds_margins(np, Ce, p.C, p.phase)}
+    out["ceff_rel_diff_fp32r_vs_fp64"] = float(np.abs(res["fp32_refine"] - res["fp64"]).max() /
+                                               np.abs(res["fp64"]).max())
     return out
 
 
@@ -214,21 +344,27 @@ def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5):
     iters = np.array([r.iters[0] for r in res])
     vox = np.array([np.prod(p.shape) for p in reqs], dtype=np.float64)
     ok = status == hz.HZ_OK
+    closed_ok = np.array([r.status[0] for r in closed_res]) == hz.HZ_OK
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)), 4) if len(x) else None
     names = {hz.HZ_OK: "ok", hz.HZ_NOT_CONVERGED: "not_converged", hz.HZ_STAGNATED: "stagnated",
              hz._abi.HZ_EDIVERGED: "diverged"}
     return {
         "workload": f"{n_req} requests: n in {{32,48,64,96,128,160,192}}^3, Boolean spheres (R=n/16, vf 0.3) or "
                     f"200-grain cubic polycrystal (Zener ratio = contrast), contrast log-uniform 1e1..1e6, one unit "
                     f"load each, FP32+refine to 1e-6, max_iters {max_iters}",
+        "latency_basis": "p50/p99 over the requests that reached 1e-6; the others (max_iters reached) are "
+                         "counted beside them and enter only the *_all_s figures",
         "closed_loop": {"makespan_s": round(makespan, 3), "solves_per_s": round(sat, 3),
-                        "p50_s": round(float(np.percentile(closed_lat, 50)), 4),
-                        "p99_s": round(float(np.percentile(closed_lat, 99)), 4)},
+                        "converged": int(closed_ok.sum()), "not_converged": int((~closed_ok).sum()),
+                        "p50_s": pct(closed_lat[closed_ok], 50), "p99_s": pct(closed_lat[closed_ok], 99),
+                        "p50_all_s": pct(closed_lat, 50), "p99_all_s": pct(closed_lat, 99)},
         "open_loop": {"arrival_rate_per_s": round(rate, 3), "load_factor": load_factor, "span_s": round(span, 3),
                       "solves_per_s": round(n_req / span, 3),
-                      "p50_s": round(float(np.percentile(lat, 50)), 4),
-                      "p99_s": round(float(np.percentile(lat, 99)), 4),
-                      "p50_converged_s": round(float(np.percentile(lat[ok], 50)), 4) if ok.any() else None,
-                      "p99_converged_s": round(float(np.percentile(lat[ok], 99)), 4) if ok.any() else None},
+                      "converged": int(ok.sum()), "not_converged": int((~ok).sum()),
+                      "p50_s": pct(lat[ok], 50), "p99_s": pct(lat[ok], 99),
+                      "p50_all_s": pct(lat, 50), "p99_all_s": pct(lat, 99)},
         "status_counts": {names.get(int(c), str(int(c))): int((status == c).sum()) for c in np.unique(status)},
         "fp64_fallbacks": int(sum(int(r.precision_used[0]) == hz.HZ_FP64 for r in res)),
         "mean_fp32_iters": round(float(iters.mean()), 1),
@@ -237,66 +373,15 @@ def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-6 comparison")
-    ap.add_argument("--ttt-n", type=int, default=256, help="grid size of the time-to-1e-6 polycrystal")
-    ap.add_argument("--scheme", choices=["auto", "spectral", "stencil"], default="auto")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-n", type=int, default=64, help="requests in the serving stream")
-    ap.add_argument("--serve-max-iters", type=int, default=1000, help="iteration budget per served request")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="run a plain 1 GiB device copy first (HBM counter calibration)")
-    a = ap.parse_args()
-    if a.gpus != 1:
-        print(json.dumps({"error": "bench.py measures one GPU; runs on more than one GPU are not supported",
-                          "n_gpus": a.gpus}), flush=True)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import hz_synth as syn
-    import paper_2405_11168_amd as hz
-
-    torch.cuda.set_device(0)
-    if a.copy_probe:
-        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        y = torch.empty_like(x)
-        x.fill_(1)
-        torch.cuda.synchronize()
-        y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
-    # context for the roofline: what a plain 1 GiB device-to-device copy reaches on this
-    # GPU (read + write bytes over time), next to the published 8 TB/s
-    x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-    y = torch.empty_like(x)
-    x.fill_(1)
-    y.copy_(x)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(10):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    copy_gbps = 10 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9
-    del x, y
-    log(f"bench: device copy {copy_gbps:.0f} GB/s")
-    log(f"bench: building workload boolean{a.n} (contrast 1e3, 6 loads)")
-    p = syn.boolean128(n=a.n)
+def headline(a, hz, np, torch, p, g, copy_gbps):
+    """The headline: exactly `steps` iterations of the six loads of the 128^3 workload
+    in FP64, after `warmup` untimed ones; the dominant kernel's roofline from HIP events
+    around its launches over the timed iterations."""
     N1, N2, N3 = p.shape
     N = N1 * N2 * N3
     S = (N1 // 2 + 1) * N2 * N3
-    g = hz.Grid(*p.shape)
-    g.set_material(p.C, p.phase)
     g.bind(hz.HZ_FP64, 6)
     torch.cuda.synchronize()
-
     schemes = {"auto": hz.HZ_SCHEME_AUTO, "spectral": hz.HZ_SCHEME_SPECTRAL, "stencil": hz.HZ_SCHEME_STENCIL}
     sch = schemes[a.scheme]
     # warmup, then exactly `steps` iterations of all six loads
@@ -339,10 +424,6 @@ def main():
 
     # roofline of the dominant kernel from the library's HIP events on its stream, over
     # the timed iterations
-    kinds = {}
-    for name, (ms, cnt) in prof.items():
-        kind, prec = name.rsplit("_", 1)
-        kinds[name] = (kind, prec, ms, cnt)
     kind, prec = dom_name.rsplit("_", 1)
     ms, cnt = timed[dom_name]
     per_launch_bytes = kernel_bytes(kind, S, N, 6, 16 if prec == "f64" else 8)
@@ -359,31 +440,15 @@ def main():
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "bytes_per_launch": per_launch_bytes,
             "avg_launch_ms": round(avg_s * 1e3, 4), "launches": cnt, "device_copy_GBps": round(copy_gbps, 1)}
-    per_kernel = {k: {"ms_per_launch": round(v[2] / v[3], 4), "share": round(v[2] / sum(x[2] for x in kinds.values()), 3)}
-                  for k, v in kinds.items()}
+    total = sum(v[0] for v in prof.values())
+    per_kernel = kernel_rates(prof, S, N, 6)
+    for k, v in per_kernel.items():
+        v["share"] = round(prof[k][0] / total, 3)
     # whole-iteration fraction: algorithmic bytes of one iteration of the scheme used
     scheme = "stencil" if any(k.startswith("stencil") for k in prof) else "spectral"
     model_bytes = iteration_bytes(scheme, S, N, 16) / N
     iter_frac = value * model_bytes / (HBM_PEAK_GBS * 1e9)
-
-    ttt = None
-    if not a.no_ttt:
-        ttt = time_to_tol(syn, hz, np, torch, a.ttt_n)
-        log(f"bench: ttt {ttt}")
-
-    serving = None
-    if not a.no_serve:
-        log(f"bench: serving leg ({a.serve_n} requests)")
-        serving = serving_leg(syn, hz, np, torch, a.serve_n, a.serve_max_iters)
-        log(f"bench: serving {serving}")
-
-    cpu = None
-    if not a.no_cpu:
-        log("bench: CPU oracle baseline (bounded sample)")
-        cpu = cpu_baseline(p)
-        log(f"bench: cpu {cpu}")
-
-    out = {
+    return {
         "metric": METRIC, "value": value, "unit": "voxel-iters/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt * 1e3 / a.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -392,9 +457,122 @@ def main():
                    "precision": "fp64", "vf": round(p.info["vf"], 4), "n_spheres": p.info["n_spheres"],
                    "parallelism": "single GPU"},
         "roofline": roof, "scheme": scheme, "other_scheme": alt, "bytes_per_voxel_iteration": round(model_bytes, 1),
-        "iteration_roofline_frac": round(iter_frac, 4),
-        "per_kernel": per_kernel, "cpu_baseline": cpu, "time_to_1e-6": ttt, "serving": serving,
+        "iteration_roofline_frac": round(iter_frac, 4), "per_kernel": per_kernel,
     }
+
+
+LEGS = ("iter", "ceff", "full", "ttt", "serve", "cpu")
+FULL = ("voronoi256", "spheres192x192x320")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="legs to run, of " + ",".join(LEGS) + " (the JSON line carries the headline value "
+                         "only with 'iter')")
+    ap.add_argument("--full", default=",".join(FULL), help="full-size workloads, of " + ",".join(FULL))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-6 comparison")
+    ap.add_argument("--scheme", choices=["auto", "spectral", "stencil"], default="auto")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-n", type=int, default=200, help="requests in the serving stream")
+    ap.add_argument("--serve-max-iters", type=int, default=1000, help="iteration budget per served request")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 1 GiB device copy first (HBM counter calibration)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "bench.py measures one GPU; runs on more than one GPU are not supported",
+                          "n_gpus": a.gpus}), flush=True)
+        sys.exit(2)
+    legs = set(a.legs.split(",")) if a.legs else set()
+    full = [w for w in a.full.split(",") if w] if a.full else []
+    if legs - set(LEGS) or set(full) - set(FULL):
+        ap.error("unknown leg or workload")
+    legs -= {"cpu"} if a.no_cpu else set()
+    legs -= {"ttt"} if a.no_ttt else set()
+    legs -= {"serve"} if a.no_serve else set()
+
+    import numpy as np
+    import torch
+
+    import hz_synth as syn
+    import paper_2405_11168_amd as hz
+
+    torch.cuda.set_device(0)
+    if a.copy_probe:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    # context for the roofline: what a plain 1 GiB device-to-device copy reaches on this
+    # GPU (read + write bytes over time), next to the published 8 TB/s
+    x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    copy_gbps = 10 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9
+    del x, y
+    log(f"bench: device copy {copy_gbps:.0f} GB/s")
+    out = {}
+    p = g = None
+    if legs & {"iter", "ceff", "cpu"}:
+        log(f"bench: building workload boolean{a.n} (contrast 1e3, 6 loads)")
+        p = syn.boolean128(n=a.n)
+        g = hz.Grid(*p.shape)
+        g.set_material(p.C, p.phase)
+    if "iter" in legs:
+        out.update(headline(a, hz, np, torch, p, g, copy_gbps))
+    if "ceff" in legs:
+        log("bench: converged C_eff of the headline workload (FP64 and FP32+refine, eps < 1e-8)")
+        out["ceff_converged"] = ceff_leg(hz, np, torch, p, g)
+        log(f"bench: ceff {out['ceff_converged']}")
+    poly = gp = None
+    if "ttt" in legs or "voronoi256" in full and "full" in legs:
+        log("bench: building the 256^3 Voronoi polycrystal")
+        poly = syn.polycrystal()
+        gp = hz.Grid(*poly.shape)
+        gp.set_material(poly.C, poly.phase)
+    if "full" in legs:
+        out["full_size"] = {}
+        for w in full:
+            if w == "voronoi256":
+                q, gq, name = poly, gp, "voronoi256_200grains_cubic_6loads"
+            else:
+                q = syn.sphere_contrast((192, 192, 320), 10.0)
+                gq = hz.Grid(*q.shape)
+                gq.set_material(q.C, q.phase)
+                name = "spheres192x192x320_vf0.25_contrast10_6loads"
+            loads = np.stack([syn.unit_load(J) for J in range(6)])
+            out["full_size"][w] = full_size_leg(hz, np, torch, name, q, gq, loads)
+            log(f"bench: full size {w}: {out['full_size'][w]}")
+            if gq is not gp:
+                del gq
+    if "ttt" in legs:
+        out["time_to_1e-6"] = time_to_tol(hz, np, torch, poly, gp)
+        log(f"bench: ttt {out['time_to_1e-6']}")
+    del gp
+    if "serve" in legs:
+        log(f"bench: serving leg ({a.serve_n} requests)")
+        out["serving"] = serving_leg(syn, hz, np, torch, a.serve_n, a.serve_max_iters)
+        log(f"bench: serving {out['serving']}")
+    if "cpu" in legs:
+        log("bench: CPU oracle baseline (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(p)
+        log(f"bench: cpu {out['cpu_baseline']}")
+    if "iter" not in legs:
+        out = {"legs": sorted(legs), **out}
     print(json.dumps(out), flush=True)
 
 

@@ -109,7 +109,10 @@ typedef struct {
   int32_t precision;        /* HZ_FP64 or HZ_FP32_REFINE                                        */
   int32_t ref_mode;         /* 0: automatic reference medium; 1: use ref_C                      */
   double ref_C[36];         /* reference medium lambda0, Voigt 6x6, when ref_mode = 1           */
-  int32_t fixed_iters;      /* >= 0: run exactly this many updates, ignore tol (parity tests)   */
+  int32_t fixed_iters;      /* >= 0: run exactly this many updates, ignore tol (parity tests,
+                               fixed-work timing).  HZ_FP32_REFINE: >= 1 FP32 updates from
+                               u = 0 (no stop rule, no corrections), then one FP64 sweep that
+                               measures eps and <sigma> of the result; not served            */
   int32_t check_every;      /* host looks at the device stop flags every this many iterations  */
   double* trace_residual;   /* optional [n_loads][max_iters+1]: eps_k of every iterate (FP64);
                                needs max_iters (or fixed_iters) <= 4096                       */

@@ -33,6 +33,7 @@ void check_opts(const hz_opts& o) {
   if (!(o.tol > 0) && o.fixed_iters < 0) fail(HZ_EINVAL, "tol must be > 0");
   if (o.max_iters < 0 || o.max_iters > kMaxIters) fail(HZ_EINVAL, "max_iters out of range [0, 1000000]");
   if (o.fixed_iters > kTraceCap - 1) fail(HZ_EINVAL, "fixed_iters out of range [0, 4096]");
+  if (o.precision == HZ_FP32_REFINE && o.fixed_iters == 0) fail(HZ_EINVAL, "HZ_FP32_REFINE needs fixed_iters >= 1");
   if ((o.trace_residual || o.trace_mean) && o.fixed_iters < 0 && o.max_iters > kTraceCap - 1)
     fail(HZ_EINVAL, "a trace needs max_iters <= 4096");
   if (o.fields_on_device != 0 && o.fields_on_device != 1) fail(HZ_EINVAL, "fields_on_device must be 0 or 1");
@@ -84,8 +85,9 @@ void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, cons
   if (o.u_init) p.u_init = o.u_init + (size_t)load * 6 * sh->geo.S;  // 3 S complex = 6 S doubles
   p.tol = o.tol;
   p.max_iters = o.max_iters;
-  p.fixed_iters = o.precision == HZ_FP64 ? o.fixed_iters : -1;
-  p.inner_max = o.inner_max > 0 ? o.inner_max : 400;
+  p.fixed_iters = o.fixed_iters;
+  // a fixed FP32 count is one round 0 of exactly that many updates, measured by one sweep
+  p.inner_max = o.fixed_iters >= 0 ? o.fixed_iters : (o.inner_max > 0 ? o.inner_max : 400);
   p.rho = o.inner_rho > 0 ? o.inner_rho : 1e-3;
   Desc& d = p.base;
   d = Desc{};
@@ -802,7 +804,7 @@ int hz_server_submit(hz_server s, hz_grid g, int32_t n_loads, const double* E, c
   if (!g->mat) fail(HZ_ENOMATERIAL, "material not set");
   check_opts(*o);
   pick_form(g->shape, o->scheme);
-  if (o->precision == HZ_FP64 && o->fixed_iters >= 0) fail(HZ_EINVAL, "fixed_iters is not served");
+  if (o->fixed_iters >= 0) fail(HZ_EINVAL, "fixed_iters is not served");
   if (o->scheme == HZ_SCHEME_STRAIN) fail(HZ_EINVAL, "the strain-based scheme is not served (hz_solve only)");
   if (o->u_init || o->Ebar_init) fail(HZ_EINVAL, "initial guesses are not served (hz_solve only)");
   check_loads(E, n_loads);

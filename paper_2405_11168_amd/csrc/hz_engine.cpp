@@ -1146,6 +1146,12 @@ void Engine::advance(Prob* p, const double* s, const double* t_iter) {
         p->enter = true;
         return;
       }
+      if (p->fixed_iters >= 0 && flag == 3) {  // a fixed count that blew up has nothing to measure
+        p->code = HZ_EDIVERGED;
+        p->iters = p->inner_total;
+        p->st = PS_DONE;
+        return;
+      }
       // a diverged first estimate keeps U = 0
       p->accum = flag != 3;
       p->st = PS_SWEEP;
@@ -1163,6 +1169,9 @@ void Engine::advance(Prob* p, const double* s, const double* t_iter) {
       bool stop = false;
       if (!(p->err == p->err) || std::isinf(p->err)) {
         p->code = HZ_EDIVERGED;
+        stop = true;
+      } else if (p->fixed_iters >= 0) {  // a fixed FP32 count: the sweep only measures it
+        p->code = HZ_OK;
         stop = true;
       } else if (p->err < p->tol) {
         p->code = HZ_OK;

@@ -335,11 +335,13 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
   }
   if (fmode == 3) {
     // plain FP32 iterations of refinement round 0: stop at the target, at the FP32
-    // rounding floor (less than 3% gain over 32 iterations) or at the cap
-    const bool reached = err <= s[ST_REF];
+    // rounding floor (less than 3% gain over 32 iterations) or at the cap; with a
+    // fixed count only at the cap
+    const bool fixed = d.fixed_iters >= 0;
+    const bool reached = !fixed && err <= s[ST_REF];
     const bool bad = !(err == err) || isinf(err) || (k > 0 && err > 1e3 * s[ST_FIRST_ERR]);
     bool stalled = false;
-    if (k > 0 && (k % 32) == 0) {
+    if (!fixed && k > 0 && (k % 32) == 0) {
       if (err > 0.97 * s[ST_BEST]) stalled = true;
       else s[ST_BEST] = err;
     }

@@ -267,6 +267,31 @@ def test_fp32_refine_stencil_form_matches_converged_oracle():
 
 
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
+def test_fp32_fixed_count_matches_oracle_iterate(scheme):
+    """A fixed FP32 count (fixed_iters = K with HZ_FP32_REFINE): K FP32 updates from u = 0,
+    then one FP64 sweep measures the iterate.  Its <sigma> and eps against the oracle's
+    iterate K, to the 1e-6 relative bound stated for FP32 fields: every FP32 pass rounds
+    the fields by a few units of 2^-24 (6e-8), and the scheme is a contraction, so the
+    FP32 iterate stays within a small multiple of that of the FP64 one."""
+    for shape, seed, kind, K in (((64, 16, 12), 51, "iso", 12), ((32, 48, 40), 52, "aniso", 10)):
+        ph, C, C0, E = random_problem(shape, 3, seed, kind)
+        g = hz.Grid(*shape)
+        g.set_material(C, ph)
+        if not g.scheme_available(scheme):
+            continue
+        r = g.solve(E, C0=C0, precision=hz.HZ_FP32_REFINE, fixed_iters=K, scheme=scheme)
+        ref = tetra.basic_scheme(ph, C, C0, E[0], fixed_iters=K, keep_fields=False)
+        em = np.abs(r.mean_sigma[0] - ref.mean_sigma).max() / np.abs(ref.mean_sigma).max()
+        eh = abs(r.residual[0] - ref.history[K]) / ref.history[0]
+        _say(f"  FP32 fixed count {shape} {kind} K={K}: <sigma> {em:.1e}, eps {eh:.1e} "
+             f"(eps_K {ref.history[K]:.2e})")
+        assert r.status[0] == hz.HZ_OK and r.iters[0] == K and r.outer_rounds[0] == 1
+        assert em < 1e-6 and eh < 1e-6
+    with pytest.raises(hz.HzError):
+        g.solve(E, C0=C0, precision=hz.HZ_FP32_REFINE, fixed_iters=0, scheme=scheme)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
 def test_fp32_refine_displacement_matches_converged_oracle(scheme):
     """The displacement an FP32+refine solve reports is its FP64 anchor U as u(q) (the
     stencil form holds U as its inverse z transform while it iterates)."""
