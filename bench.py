@@ -277,7 +277,7 @@ def ceff_leg(hz, np, torch, p, g, tol=1e-8, max_iters=200000):
     return out
 
 
-def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5):
+def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5, streams=1):
     """Closed loop (all requests at t=0) for the saturation rate, then an open
     loop with Poisson arrivals at load_factor x that rate.  Latency = result
     ready (the server step that retired the request) - arrival time."""
@@ -291,7 +291,7 @@ def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5):
     gen_s = time.perf_counter() - t0
     need = [hz.request_bytes(g, hz.HZ_FP32_REFINE, 1) for g in grids]
     arena = min(int(1.05 * sum(need)), 160 << 30)
-    srv = hz.Server(arena, max_problems=n_req + 8, check_every=8)
+    srv = hz.Server(arena, max_problems=n_req + 8, check_every=8, streams=streams)
 
     def submit(i):
         p = reqs[i]
@@ -369,7 +369,7 @@ def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5):
         "fp64_fallbacks": int(sum(int(r.precision_used[0]) == hz.HZ_FP64 for r in res)),
         "mean_fp32_iters": round(float(iters.mean()), 1),
         "voxel_iters_per_s_closed_loop": float((vox * iters).sum() / makespan),
-        "arena_gib": round(arena / 2 ** 30, 2), "generation_s": round(gen_s, 1),
+        "arena_gib": round(arena / 2 ** 30, 2), "generation_s": round(gen_s, 1), "streams": streams,
     }
 
 
@@ -429,13 +429,16 @@ def headline(a, hz, np, torch, p, g, copy_gbps):
     per_launch_bytes = kernel_bytes(kind, S, N, 6, 16 if prec == "f64" else 8)
     avg_s = ms / cnt / 1e3
     achieved = per_launch_bytes / avg_s / 1e9
+    # HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs of this
+    # workload, while the sources are the ones they were taken on
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"{kind}_{prec}_boolean128_traffic.json")
+    tfile = os.path.join(ROOT, "profiles", f"iteration_boolean{N1}_traffic.json")
     if os.path.exists(tfile):
         with open(tfile) as fh:
             t = json.load(fh)
-        if t.get("source_digest") == source_digest():
-            traffic = t.get("bytes_per_launch")
+        k = t.get("kernels", {}).get(dom_name)
+        if t.get("source_digest") == source_digest() and k and k.get("problems") == 6:
+            traffic = k.get("bytes_per_launch")
     roof = {"bound": "hbm", "kernel": f"{kind}_{prec}", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "bytes_per_launch": per_launch_bytes,
@@ -475,12 +478,15 @@ def main():
                     help="legs to run, of " + ",".join(LEGS) + " (the JSON line carries the headline value "
                          "only with 'iter')")
     ap.add_argument("--full", default=",".join(FULL), help="full-size workloads, of " + ",".join(FULL))
+    ap.add_argument("--full-steps", type=int, default=24,
+                    help="passes of the longer full-size run (the shorter one runs a sixth of them)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-6 comparison")
     ap.add_argument("--scheme", choices=["auto", "spectral", "stencil"], default="auto")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-n", type=int, default=200, help="requests in the serving stream")
     ap.add_argument("--serve-max-iters", type=int, default=1000, help="iteration budget per served request")
+    ap.add_argument("--serve-streams", type=int, default=4, help="streams the server spreads its groups over")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
     a = ap.parse_args()
@@ -555,7 +561,8 @@ def main():
                 gq.set_material(q.C, q.phase)
                 name = "spheres192x192x320_vf0.25_contrast10_6loads"
             loads = np.stack([syn.unit_load(J) for J in range(6)])
-            out["full_size"][w] = full_size_leg(hz, np, torch, name, q, gq, loads)
+            out["full_size"][w] = full_size_leg(hz, np, torch, name, q, gq, loads, K1=max(2, a.full_steps // 6),
+                                                K2=max(a.full_steps, 4))
             log(f"bench: full size {w}: {out['full_size'][w]}")
             if gq is not gp:
                 del gq
@@ -565,7 +572,7 @@ def main():
     del gp
     if "serve" in legs:
         log(f"bench: serving leg ({a.serve_n} requests)")
-        out["serving"] = serving_leg(syn, hz, np, torch, a.serve_n, a.serve_max_iters)
+        out["serving"] = serving_leg(syn, hz, np, torch, a.serve_n, a.serve_max_iters, streams=a.serve_streams)
         log(f"bench: serving {out['serving']}")
     if "cpu" in legs:
         log("bench: CPU oracle baseline (bounded sample)")

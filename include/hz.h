@@ -313,6 +313,18 @@ int hz_server_release(hz_server s, int64_t id);
 /* Requests waiting for admission and requests running. */
 int hz_server_pending(hz_server s, int32_t* queued, int32_t* running);
 
+/* Spread the iterate groups of a tick (the loads of one grid shape and kernel
+ * precision; one launch per pass each) over n_streams streams: the server's own and
+ * n_streams - 1 non-blocking streams of default priority that the library creates
+ * and destroys with the server.  Each tick forks them from the server's stream with
+ * an event, gives each group to the stream with the least estimated work so far,
+ * issues one iteration of every group in turn, and joins them back into the server's
+ * stream before it reads the stop flags, so groups of different shapes run on the
+ * device at the same time.  n_streams = 1 (the default) runs the groups one after
+ * another on the server's stream.  Groups hold disjoint loads: results do not depend
+ * on n_streams.  1 <= n_streams <= 8, else HZ_EINVAL. */
+int hz_server_set_streams(hz_server s, int32_t n_streams);
+
 /* Wait for the stream and free the server's host state (the workspace stays the caller's). */
 void hz_server_destroy(hz_server s);
 

@@ -276,9 +276,10 @@ class Server:
     """Solve server (hz_server handle): continuous batching of requests on a
     torch-owned workspace.  submit() queues a request, step() runs one tick
     (admission, check_every iterations of every active load, retirement),
-    result() returns a finished request's SolveResult or None."""
+    result() returns a finished request's SolveResult or None.  streams > 1 spreads the
+    iterate groups of a tick over that many streams (hz_server_set_streams)."""
 
-    def __init__(self, arena_bytes: int, max_problems=64, check_every=8, device="cuda", stream=None):
+    def __init__(self, arena_bytes: int, max_problems=64, check_every=8, device="cuda", stream=None, streams=1):
         import torch
 
         fixed = check(lib().hz_server_bytes(max_problems))
@@ -290,6 +291,8 @@ class Server:
                                      ctypes.c_void_p(s.cuda_stream), max_problems, check_every, ctypes.byref(h)))
         self._h = h
         self._nloads = {}
+        if streams != 1:
+            check(lib().hz_server_set_streams(h, streams))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -94,6 +94,7 @@ SIGNATURES = {
     "hz_server_query": (c_int32, [c_void_p, c_int64, POINTER(c_double), POINTER(hz_info)]),
     "hz_server_release": (c_int32, [c_void_p, c_int64]),
     "hz_server_pending": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "hz_server_set_streams": (c_int32, [c_void_p, c_int32]),
     "hz_server_destroy": (None, [c_void_p]),
 }
 

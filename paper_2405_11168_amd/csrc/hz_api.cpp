@@ -897,6 +897,15 @@ int hz_server_pending(hz_server s, int32_t* queued, int32_t* running) {
   HZ_GUARD_END
 }
 
+int hz_server_set_streams(hz_server s, int32_t n_streams) {
+  HZ_GUARD_BEGIN
+  if (!s) fail(HZ_EINVAL, "NULL handle");
+  if (n_streams < 1 || n_streams > kMaxLanes) fail(HZ_EINVAL, "n_streams out of range [1, 8]");
+  s->eng.set_lanes(n_streams);
+  return HZ_OK;
+  HZ_GUARD_END
+}
+
 void hz_server_destroy(hz_server s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);

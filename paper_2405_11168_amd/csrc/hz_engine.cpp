@@ -832,12 +832,32 @@ hipEvent_t Engine::event(size_t i) {
   return evs[i];
 }
 
+void Engine::set_lanes(int n) {
+  if (n < 1 || n > kMaxLanes) fail(HZ_EINVAL, "stream count out of range [1, 8]");
+  while ((int)side.size() < n - 1) {
+    hipStream_t st;
+    hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    side.push_back(st);
+  }
+  while (fork_join.size() < side.size() + 1) {
+    hipEvent_t ev;
+    hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreateWithFlags");
+    fork_join.push_back(ev);
+  }
+  lanes = n;
+}
+
 void Engine::start_clock() {
   if (!epoch) hip_check(hipEventCreate(&epoch), "hipEventCreate");
   hip_check(hipEventRecord(epoch, stream), "hipEventRecord");
 }
 
 Engine::~Engine() {
+  for (auto st : side) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (auto ev : fork_join) (void)hipEventDestroy(ev);
   for (auto ev : evs) (void)hipEventDestroy(ev);
   if (epoch) (void)hipEventDestroy(epoch);
   if (pinned) {
@@ -1022,6 +1042,7 @@ std::vector<Prob*> Engine::tick() {
   for (Prob* p : live) p->enter = false;
   size_t nev = 0;
   hip_check(hipEventRecord(event(nev++), stream), "hipEventRecord");  // tick start
+  std::vector<Seg*> its;
   for (auto& s : segs) {
     if (s.cat < 4) continue;
     int need = 1;
@@ -1034,23 +1055,72 @@ std::vector<Prob*> Engine::tick() {
     }
     s.K = std::max(1, std::min(check_every, need));
     s.ev0 = (int)nev;
+    nev += s.K;
+    its.push_back(&s);
+  }
+  if (nev > 0) event(nev - 1);  // every event of the tick exists before any is recorded
+  // lanes: with one, the groups run in turn on `stream`; with more, each group goes to
+  // the lane with the least estimated work so far (voxels x problems x iterations,
+  // FP64 counted twice) and the lanes take one iteration of each of their groups in
+  // turn.  Groups hold disjoint problems, so the order changes no result.
+  const int L = std::min<int>(lanes, (int)its.size());
+  std::vector<int> lane_of(its.size(), 0);
+  if (L > 1) {
+    std::vector<double> cost(its.size()), load(L, 0.0);
+    std::vector<int> order(its.size());
+    for (size_t j = 0; j < its.size(); ++j) {
+      cost[j] = (double)its[j]->proto->shape->geo.N * its[j]->ps.size() * its[j]->K * (its[j]->cat == 4 ? 2 : 1);
+      order[j] = (int)j;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int j : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      lane_of[j] = l;
+      load[l] += cost[j];
+    }
+    hip_check(hipEventRecord(fork_join[0], stream), "hipEventRecord");
+    for (int l = 1; l < L; ++l) hip_check(hipStreamWaitEvent(side[l - 1], fork_join[0], 0), "hipStreamWaitEvent");
+  }
+  const hipStream_t main_stream = stream;
+  auto run_iteration = [&](Seg& s, int i) {
     const int* act = d_active + s.off;
     const int n = (int)s.ps.size();
-    for (int i = 0; i < s.K; ++i) {
-      const int form = s.proto->form;
-      int c0 = 0;
-      for (const Prob* q : s.ps) c0 |= q->base.c0_iso ? 1 : 2;
-      const Shape& sh = *s.proto->shape;
-      const ShapeTables& tb = s.proto->tab;
-      if (s.cat == 4) {
-        if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, c0);
-        else if (form == HZ_SCHEME_STRAIN) iteration_strain<double>(*this, sh, tb, act, n, s.cnt, c0);
-        else iteration<double>(*this, sh, tb, act, n, s.cnt, c0);
-      } else {
-        if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, c0);
-        else iteration<float>(*this, sh, tb, act, n, s.cnt, c0);
+    const int form = s.proto->form;
+    int c0 = 0;
+    for (const Prob* q : s.ps) c0 |= q->base.c0_iso ? 1 : 2;
+    const Shape& sh = *s.proto->shape;
+    const ShapeTables& tb = s.proto->tab;
+    if (s.cat == 4) {
+      if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, c0);
+      else if (form == HZ_SCHEME_STRAIN) iteration_strain<double>(*this, sh, tb, act, n, s.cnt, c0);
+      else iteration<double>(*this, sh, tb, act, n, s.cnt, c0);
+    } else {
+      if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, c0);
+      else iteration<float>(*this, sh, tb, act, n, s.cnt, c0);
+    }
+    hip_check(hipEventRecord(evs[s.ev0 + i], stream), "hipEventRecord");
+  };
+  if (L <= 1) {
+    for (Seg* s : its)
+      for (int i = 0; i < s->K; ++i) run_iteration(*s, i);
+  } else {
+    struct Restore {  // `stream` names the server's stream again however the loop ends
+      Engine& e;
+      hipStream_t s;
+      ~Restore() { e.stream = s; }
+    } restore{*this, main_stream};
+    int kmax = 0;
+    for (Seg* s : its) kmax = std::max(kmax, s->K);
+    for (int i = 0; i < kmax; ++i)
+      for (size_t j = 0; j < its.size(); ++j) {
+        if (i >= its[j]->K) continue;
+        stream = lane_of[j] == 0 ? main_stream : side[lane_of[j] - 1];  // the launches below go there
+        run_iteration(*its[j], i);
       }
-      hip_check(hipEventRecord(event(nev++), stream), "hipEventRecord");
+    stream = main_stream;
+    for (int l = 1; l < L; ++l) {
+      hip_check(hipEventRecord(fork_join[l], side[l - 1]), "hipEventRecord");
+      hip_check(hipStreamWaitEvent(stream, fork_join[l], 0), "hipStreamWaitEvent");
     }
   }
   hip_check(hipMemcpyAsync(h_status, d_status, (size_t)hi * kStatusLen * 8, hipMemcpyDeviceToHost, stream),

@@ -57,6 +57,7 @@ void hip_check(hipError_t e, const char* what);
 
 constexpr int kTraceCap = 4097;        // iterates recorded per load (eps_k, <sigma>_k)
 constexpr int kMaxIters = 1000000;     // cap on max_iters
+constexpr int kMaxLanes = 8;           // streams a server may spread iterate groups over
 constexpr int kLdsBytes = 65536 - 512;  // LDS budget of one work-group
 
 float recip(int d);
@@ -232,10 +233,17 @@ struct Engine {
   hipEvent_t epoch = nullptr;
   std::vector<hipEvent_t> evs;
   std::vector<double> ev_ms;
+  // lanes > 1: the iterate groups of a tick are spread over `stream` and lanes - 1
+  // more streams (non-blocking, default priority), forked from and joined into
+  // `stream` with events
+  int lanes = 1;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> fork_join;
 
   static size_t table_bytes(int cap);
   void init(int cap, bool pinned_mirrors = true);
   void bind(char* dev, hipStream_t s);
+  void set_lanes(int n);
   void start_clock();
   void add(Prob* p);
   // one tick; returns the problems that finished in it

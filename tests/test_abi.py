@@ -183,3 +183,9 @@ def test_profile_modes():
     g.profile(False)
     with pytest.raises(ValueError):
         g.profile(True, only="no_such_kernel_f64")
+
+
+def test_server_stream_count_checks_without_a_server():
+    lib = hz.lib()
+    assert lib.hz_server_set_streams(None, 2) == _abi.HZ_EINVAL
+    assert b"NULL" in lib.hz_last_error()

@@ -79,10 +79,13 @@ def _same(a, b):
         np.array_equal(a.status, b.status) and np.array_equal(a.residual, b.residual)
 
 
-def test_mix_equals_alone_bitwise():
+@pytest.mark.parametrize("streams", [1, 3], ids=["one_stream", "three_streams"])
+def test_mix_equals_alone_bitwise(streams):
+    """streams = 3: the groups of a tick (three shapes, two precisions) spread over three
+    streams and run on the device at the same time."""
     grids = _make()
     alone = _alone(grids)
-    srv = hz.Server(_arena(grids), max_problems=32, check_every=4)
+    srv = hz.Server(_arena(grids), max_problems=32, check_every=4, streams=streams)
     ids = [srv.submit(grids[key], _loads(nl, 100 + i), tol=tol, precision=prec, scheme=sc)
            for i, (key, _s, _seed, _a, nl, prec, tol, sc) in enumerate(CASES)]
     srv.drain()
@@ -108,7 +111,7 @@ def test_continuous_arrivals_and_admission_under_memory_pressure():
     grids = _make()
     alone = _alone(grids)
     biggest = max(hz.request_bytes(grids[k], p, n) for k, _s, _sd, _a, n, p, _t, _sc in CASES)
-    srv = hz.Server(int(2.05 * biggest), max_problems=16, check_every=2)
+    srv = hz.Server(int(2.05 * biggest), max_problems=16, check_every=2, streams=2)
     ids = {}
     saw_queue = False
     pending = list(range(len(CASES)))
@@ -146,6 +149,8 @@ def test_release_of_queued_request_and_errors():
     with pytest.raises(hz.HzError) as e:
         srv.submit(g, _loads(2, 3), tol=1e-6)  # two loads never fit
     assert e.value.code == hz._abi.HZ_EWORKSPACE
+    for bad in (0, 9):
+        assert hz.lib().hz_server_set_streams(srv._h, bad) == hz._abi.HZ_EINVAL
 
 
 KINDS = [("iso", False, False), ("iso_eig", False, True), ("aniso", True, False), ("aniso_eig", True, True)]
