@@ -348,6 +348,21 @@ def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5, s
 
     def pct(x, q):
         return round(float(np.percentile(x, q)), 4) if len(x) else None
+    # which requests reach 1e-6 within the budget, by microstructure kind and contrast
+    # decade: the basic scheme's rate degrades like 1 - O(1/C) on percolating stiff phases
+    resid = np.array([r.residual[0] for r in res])
+    by_contrast = []
+    for kind in ("spheres", "polycrystal"):
+        for d in range(1, 6):
+            sel = np.array([p.info["kind"] == kind and d <= np.log10(p.info["contrast"]) < d + 1 for p in reqs])
+            if not sel.any():
+                continue
+            by_contrast.append({"kind": kind, "contrast": f"1e{d}..1e{d + 1}", "n": int(sel.sum()),
+                                "converged": int(ok[sel].sum()),
+                                "median_iters_converged": (int(np.median(iters[sel & ok])) if (sel & ok).any()
+                                                           else None),
+                                "median_residual_not_converged": (float(np.median(resid[sel & ~ok]))
+                                                                  if (sel & ~ok).any() else None)})
     names = {hz.HZ_OK: "ok", hz.HZ_NOT_CONVERGED: "not_converged", hz.HZ_STAGNATED: "stagnated",
              hz._abi.HZ_EDIVERGED: "diverged"}
     return {
@@ -366,6 +381,7 @@ def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5, s
                       "p50_s": pct(lat[ok], 50), "p99_s": pct(lat[ok], 99),
                       "p50_all_s": pct(lat, 50), "p99_all_s": pct(lat, 99)},
         "status_counts": {names.get(int(c), str(int(c))): int((status == c).sum()) for c in np.unique(status)},
+        "by_contrast": by_contrast,
         "fp64_fallbacks": int(sum(int(r.precision_used[0]) == hz.HZ_FP64 for r in res)),
         "mean_fp32_iters": round(float(iters.mean()), 1),
         "voxel_iters_per_s_closed_loop": float((vox * iters).sum() / makespan),

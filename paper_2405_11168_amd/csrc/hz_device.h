@@ -192,7 +192,8 @@ __device__ __forceinline__ void constitutive(const HZ_GLB T* __restrict__ Cp, co
 }
 
 // the same law for the two tetrahedra of one voxel (one phase): the stiffness entries
-// are loaded once for both
+// are loaded once for both and each is used as it arrives (C_ab enters sigma_a and, off
+// the diagonal, sigma_b), so only a few of them are live at a time
 template <bool EIG, typename T>
 __device__ __forceinline__ void constitutive_pair(const HZ_GLB T* __restrict__ Cp, const Mean<T>& M, int ph,
                                                   const T (&de0)[6], const T (&de1)[6], T (&s0)[6], T (&s1)[6]) {
@@ -201,31 +202,33 @@ __device__ __forceinline__ void constitutive_pair(const HZ_GLB T* __restrict__ C
   for (int c = 0; c < 6; ++c) {
     g0[c] = M.Eb[c] + de0[c];
     g1[c] = M.Eb[c] + de1[c];
+    s0[c] = 0;
+    s1[c] = 0;
   }
 #pragma unroll
   for (int c = 3; c < 6; ++c) {  // engineering shears
     g0[c] *= (T)2;
     g1[c] *= (T)2;
   }
-  T Cu[24];
+  // packed entry k of the upper triangle is (a, b): row a = 0 holds k = 0..5, a = 1
+  // k = 6..10, a = 2 k = 11..14, a = 3 k = 15..17, a = 4 k = 18..19, a = 5 k = 20
 #pragma unroll
-  for (int i = 0; i < 24; i += 2) {
-    const cpx<T> v = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(Cp) + i / 2);
-    Cu[i] = v.x;
-    Cu[i + 1] = v.y;
-  }
+  for (int k2 = 0; k2 < 21; k2 += 2) {
+    const cpx<T> v = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(Cp) + k2 / 2);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    T a0 = 0, a1 = 0;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const int a = i < j ? i : j, b = i < j ? j : i;
-      const T cij = Cu[a * 6 - a * (a - 1) / 2 + (b - a)];
-      a0 += cij * g0[j];
-      a1 += cij * g1[j];
+    for (int h = 0; h < 2; ++h) {
+      const int k = k2 + h;
+      if (k > 20) break;
+      const int a = k < 6 ? 0 : k < 11 ? 1 : k < 15 ? 2 : k < 18 ? 3 : k < 20 ? 4 : 5;
+      const int b = a + k - (a * 6 - a * (a - 1) / 2);
+      const T c = h ? v.y : v.x;
+      s0[a] += c * g0[b];
+      s1[a] += c * g1[b];
+      if (a != b) {
+        s0[b] += c * g0[a];
+        s1[b] += c * g1[a];
+      }
     }
-    s0[i] = a0;
-    s1[i] = a1;
   }
   eigenstress<EIG>(M, ph, s0);
   eigenstress<EIG>(M, ph, s1);

@@ -123,15 +123,12 @@ struct YGeo {
 //   6..8  corner force g = sum_T sigma^T(c - o) . w(o), real        [3][l3][l2][l1]
 //   9..11 g: forward x (1/N) then forward y                         [3][h1][l3][h2]
 // Real fields of N values start at element offset slot*S + c*N/2.
-// stencil tile: corners along x and y per block (kStX * kStY == kThreads), and
-// corner planes per block along z (compile-time tuning defaults)
-#ifndef HZ_STX
-#define HZ_STX 64
-#endif
+// stencil tile: 64 corners along x (one per lane of a wave), one corner row per wave
+// along y (kStY = kThreads / 64), and at most kStZ corner planes per block along z
 #ifndef HZ_STZ
 #define HZ_STZ 16
 #endif
-constexpr int kStX = HZ_STX, kStY = kThreads / HZ_STX, kStZ = HZ_STZ;
+constexpr int kStX = 64, kStY = kThreads / 64, kStZ = HZ_STZ;
 struct SGeo {
   int N1, N2, N3;
   int TZ;                 // corner planes per block (z segment)

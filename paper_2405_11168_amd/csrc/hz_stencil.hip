@@ -76,8 +76,23 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ desc
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* twl = buf + 3 * TY * xg.H1p;
   stage_table(twl, twN1, xg.N1);
-  __syncthreads();
   HZ_GLB cpx<T>* spec = glb(reinterpret_cast<cpx<T>*>(d.spec));
+  {
+    // the corner-force rows that the stencil kernel accumulates from two blocks (the
+    // last corner row of each of its tiles in y) start from zero
+    HZ_GLB T* g = reinterpret_cast<HZ_GLB T*>(spec + 6 * xg.S);
+    const long long N = (long long)xg.N1 * xg.N2 * xg.N3;
+#pragma unroll 1
+    for (int r = 0; r < TY; ++r) {
+      const int l2 = l2_0 + r;
+      if (l2 % kStY != kStY - 1 && l2 != xg.N2 - 1) continue;
+      HZ_GLB T* row = g + (long long)(row0 + r) * xg.N1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        for (int x = threadIdx.x; x < xg.N1; x += kThreads) row[c * N + x] = (T)0;
+    }
+  }
+  __syncthreads();
   const Plan& pi = *planXi;
   const int np = pi.np;
   xf_load<T, R0, 3>(xg, spec + row0, buf, twl);
@@ -136,9 +151,9 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ desc
   xf_store<T, RL, 3>(xg, spec + 9 * xg.S + row0, buf, twl);
 }
 
-// corner o in {0,-1}^3 coded as bits (bit a set: o_a = 0, clear: o_a = -1);
-// T1 takes the corners with an even number of -1 offsets
-__device__ __forceinline__ int tet_of(int o) { return ((o & 1) + ((o >> 1) & 1) + ((o >> 2) & 1)) & 1 ? 0 : 1; }
+// corner o in {0,-1}^3 coded as bits (bit a set: o_a = 0, clear: o_a = -1).  T1 takes the
+// corners with an even number of -1 offsets (codes 001, 010, 100, 111), T2 the others
+// (000, 011, 101, 110); the weight of corner o is w(o) = o + (1/2, 1/2, 1/2).
 
 // strain of tetrahedron k of one voxel from its 4 corners (u4[i] = corner o_i of Tk,
 // in increasing corner code).  The weights w(o) pair the corners: with
@@ -164,38 +179,121 @@ __device__ __forceinline__ void stencil_strain_k(const T (&u4)[4][3], T (&e)[6])
   e[5] = (T)0.25 * (H[0][1] + H[1][0]);
 }
 
-// sigma^Tk of one voxel of an isotropic phase
-template <typename T, bool EIG, int K>
-__device__ __forceinline__ void stencil_sigma_iso_k(const Mean<T>& Mn, int ph, cpx<T> lm, const T (&u4)[4][3],
-                                                    T (&out)[6]) {
-  T e[6];
-  stencil_strain_k<T, K>(u4, e);
-  constitutive_iso<EIG, T>(lm.x, lm.y, Mn, ph, e, out);
+// sigma^T1 and sigma^T2 of one voxel from its 8 corners c[o] (o = corner code)
+template <typename T, bool ISO, bool EIG>
+__device__ __forceinline__ void voxel_sigma(const T (&c)[8][3], const HZ_GLB T* __restrict__ C, cpx<T> lm, int ph,
+                                            const Mean<T>& Mn, T (&s1)[6], T (&s2)[6]) {
+  T e1[6], e2[6];
+  {
+    T u4[4][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      u4[0][j] = c[1][j];
+      u4[1][j] = c[2][j];
+      u4[2][j] = c[4][j];
+      u4[3][j] = c[7][j];
+    }
+    stencil_strain_k<T, 0>(u4, e1);
+  }
+  {
+    T u4[4][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      u4[0][j] = c[0][j];
+      u4[1][j] = c[3][j];
+      u4[2][j] = c[5][j];
+      u4[3][j] = c[6][j];
+    }
+    stencil_strain_k<T, 1>(u4, e2);
+  }
+  if constexpr (ISO) {
+    constitutive_iso<EIG, T>(lm.x, lm.y, Mn, ph, e1, s1);
+    constitutive_iso<EIG, T>(lm.x, lm.y, Mn, ph, e2, s2);
+  } else {
+    constitutive_pair<EIG, T>(C + ph * 24, Mn, ph, e1, e2, s1, s2);
+  }
 }
 
-// Strain, constitutive law and corner force in real space.  A block owns a
-// kStX x kStY column of corners over TZ planes and streams along z: at voxel
-// plane p the corner planes p-1 and p sit in LDS (ring of two); for T1 and then T2
-// it computes sigma^Tk of the voxel plane (one halo voxel on the + side in x and y)
-// and the corners gather it, which completes the force of corner plane p-1 and
-// starts that of corner plane p.  Corner plane p+1
-// is fetched into registers one step ahead, so its latency overlaps the work.
-// Occupancy: isotropic phases keep one tetrahedron's stresses in LDS at a time (35 KB
-// per block in FP64), which lets 4 blocks share a CU.  The anisotropic variants, held
-// to 3 waves per SIMD by their registers anyway, compute both tetrahedra of a voxel
-// in one stage (50 KB): the 21 stiffness entries are loaded once per voxel and a
-// z step has 2 barriers instead of 4.  The register bounds below are the largest that
-// compile without spills (FP64: 4 waves per SIMD for isotropic phases without
-// eigenstrains, 3 otherwise; FP32: 5 for the isotropic variant without eigenstrains).
+// Rows of a stress for the corner forces: with X, Y, Z the rows of sigma (sigma e_a),
+// 2 sigma.w(o) = +-X +-Y +-Z with the signs of o + 1/2; P = X + Y, M = X - Y.
+template <typename T>
+__device__ __forceinline__ void stress_rows(const T (&s)[6], T (&P)[3], T (&M)[3], T (&Z)[3]) {
+  const T X[3] = {s[0], s[5], s[4]}, Y[3] = {s[5], s[1], s[3]};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    P[j] = X[j] + Y[j];
+    M[j] = X[j] - Y[j];
+  }
+  Z[0] = s[4];
+  Z[1] = s[3];
+  Z[2] = s[2];
+}
+
+// Raw buffer access to one plane of a real field: the plane's address sits in a
+// buffer resource (scalar registers) and each lane adds a 32-bit byte offset, so no
+// 64-bit address is formed per lane; an offset past the plane reads 0 and is not
+// written.  Word 3 of the resource is the gfx9 raw-buffer setting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld(double, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ float buf_ld(float, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                        (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+
+// Lane shifts across the wavefront (DPP): with kShr1 lane i takes the value of lane
+// i - 1, with kShl1 that of lane i + 1; the lane without a source (0, resp. 63) takes
+// `edge`.  Every lane of the wave must be active.
+constexpr int kShr1 = 0x138, kShl1 = 0x130;
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v, double edge) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(edge), __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(edge), __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v, float edge) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// waves per SIMD the register budget is set for: FP64 needs about 166 VGPRs (3 waves),
+// FP32 about 105 (4 waves); no variant spills at these bounds except the anisotropic
+// FP64 one with eigenstrains (a few loop-invariant addresses)
+template <typename T>
+constexpr int stencil_waves() { return sizeof(T) == 8 ? 3 : 4; }
+// Strain, constitutive law and corner force in real space.  A block owns a tile of
+// 64 x kStY corners in x and y over TZ planes along z: wave w owns corner row y0 + w,
+// lane l the corner column x = x0 + l, and the wave streams along z.  At voxel plane p
+// a lane holds the 8 corners of voxel (x, y, p) -- its own column and, by a lane shift,
+// column x - 1, in its row and the row below (both loaded by the wave), planes p - 1 and
+// p -- and computes sigma of both tetrahedra and the voxel's contribution 2 sigma.w(o)
+// to each corner x + o.  The contributions to one corner plane are summed per corner
+// offset (dx, dy) = (-o1, -o2) over the two voxel planes that touch it, A_dxdy, and
+//   g(x, y, p-1) = 1/2 [A00(x, y) + A10(x+1, y) + A01(x, y+1) + A11(x+1, y+1)]:
+// A10 and A11 of column x + 1 come by a lane shift, the row y + 1 terms from the wave of
+// that row through LDS (one barrier per z step, double buffered).  The voxel column
+// right of the tile is computed once per wave before the z loop, with its lanes spread
+// over the planes, and the corners of column x0 - 1 are staged there too.  The last
+// corner row of a tile takes terms from two blocks: the wave of that row adds its part
+// and the first wave of the next tile in y adds the row y + 1 terms, both as atomic adds
+// onto a row the C2R kernel has zeroed.  With exactly two addends the result does not
+// depend on their order, so every run gives the same bits.
 template <typename T, bool ISO, bool EIG>
-__global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) : (sizeof(T) == 8 ? 3 : 1)) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
+__global__ __launch_bounds__(kThreads, stencil_waves<T>()) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
                                                       SGeo sg) {
-  constexpr int UX = kStX + 2, UY = kStY + 2, VX = kStX + 1, VY = kStY + 1;
-  constexpr int UP = 3 * UY * UX;                      // corner values per plane
-  constexpr int NL = (UP + kThreads - 1) / kThreads;   // per thread
-  constexpr bool PAIR = !ISO;                          // both tetrahedra per stage
-  __shared__ T ub[2][UP];                              // [slot][c][yy][xx]
-  __shared__ T sb[PAIR ? 2 : 1][6][VY][VX];            // sigma of one (or both) tetrahedra
+  static_assert(kStX == 64 && kStY * 64 == kThreads, "one wave per corner row");
+  __shared__ T lh[kStY][kStZ + 2][6];     // u at column x0 - 1: row below (0..2), own row (3..5)
+  __shared__ T hr[kStY][kStZ + 1][4][3];  // halo voxel column: contribution to column x0+wx-1, [dy*2 + dz]
+  __shared__ T xb[2][kStY][3][64];        // row y + 1 terms of corner row y
   __shared__ double red[6 * 4];
   const Desc& d = descs[active[blockIdx.y]];
   if (problem_done(d) || (d.iso != 0) != ISO || (d.tau64 != nullptr) != EIG) return;
@@ -210,221 +308,225 @@ __global__ __launch_bounds__(kThreads, (ISO && !EIG) ? (sizeof(T) == 4 ? 5 : 4) 
   const HZ_GLB T* ur = reinterpret_cast<const HZ_GLB T*>(glb(reinterpret_cast<const cpx<T>*>(d.spec)) + 3 * S);
   HZ_GLB T* gr = reinterpret_cast<HZ_GLB T*>(glb(reinterpret_cast<cpx<T>*>(d.spec)) + 6 * S);
   const HZ_GLB T* C = glb(sizeof(T) == 8 ? reinterpret_cast<const T*>(d.C64) : reinterpret_cast<const T*>(d.C32));
+  const HZ_GLB cpx<T>* Clm = reinterpret_cast<const HZ_GLB cpx<T>*>(C);
   const Mean<T> Mn = mean_state<T>(d);
   const HZ_GLB uint16_t* ph = glb(d.phase);
-  const int tid = threadIdx.x;
-  const int cx = tid % kStX, cy = tid / kStX;  // the corner this thread owns
-  const bool own = cx < wx && cy < wy;
-  // in-plane offsets of this thread's corner loads (periodic wrap)
-  int loff[NL];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool wact = w < wy, xact = lane < wx;
+  const int y = y0 + (wact ? w : 0);  // waves past the tile's last row shadow its first (results unused)
+  const int ym = y == 0 ? N2 - 1 : y - 1;
+  // lanes past a ragged tile's last column take the voxel column right of the tile
+  // (periodic), so the lane after the last one holds that column's terms
+  const int x = xact ? x0 + lane : (x0 + wx == N1 ? 0 : x0 + wx);
+  auto plane = [&](int q) { return q < 0 ? q + N3 : (q >= N3 ? q - N3 : q); };
+
+  // ---- the corners of column x0 - 1, and the voxel column x0 + wx (periodic), one
+  // lane per plane: lane l holds corner plane z0 - 1 + l, l <= wz + 1
+  {
+    const int xl = x0 == 0 ? N1 - 1 : x0 - 1;
+    const int xh = x0 + wx == N1 ? 0 : x0 + wx, xhm = x0 + wx - 1;
+    const int l = min(lane, wz + 1);
+    const int q = plane(z0 - 1 + l);
+    const HZ_GLB T* b = ur + (long long)q * NP;
+    T L[6], R[2][2][3];  // R[row: below/own][column: xhm/xh][comp]
 #pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int i = tid + k * kThreads;
-    loff[k] = -1;
-    if (i < UP) {
-      const int c = i / (UY * UX), rem = i - c * (UY * UX);
-      const int yy = rem / UX, xx = rem - yy * UX;
-      int gx = x0 - 1 + xx, gy = y0 - 1 + yy;
-      while (gx < 0) gx += N1;
-      while (gx >= N1) gx -= N1;
-      while (gy < 0) gy += N2;
-      while (gy >= N2) gy -= N2;
-      loff[k] = c * Nn + gy * N1 + gx;
+    for (int j = 0; j < 3; ++j) {
+      L[j] = b[j * Nn + ym * N1 + xl];
+      L[3 + j] = b[j * Nn + y * N1 + xl];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        R[r][0][j] = b[j * Nn + (r ? y : ym) * N1 + xhm];
+        R[r][1][j] = b[j * Nn + (r ? y : ym) * N1 + xh];
+      }
+    }
+    const int hph = ph[(long long)q * NP + y * N1 + xh];
+    const cpx<T> hlm = ISO ? gld(Clm + hph) : cpx<T>{0, 0};
+    if (wact && lane <= wz + 1) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) lh[w][lane][k] = L[k];
+    }
+    // voxel (xh, y, q) of lane l >= 1 (voxel plane z0 + l - 1): the plane below from lane l - 1
+    T c[8][3];
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const T v = R[(o >> 1) & 1][o & 1][j];
+        c[o][j] = (o & 4) ? v : lane_shift<kShr1>(v, v);
+      }
+    T s1[6], s2[6];
+    voxel_sigma<T, ISO, EIG>(c, C, hlm, hph, Mn, s1, s2);
+    T P1[3], M1[3], Z1[3], P2[3], M2[3], Z2[3];
+    stress_rows(s1, P1, M1, Z1);
+    stress_rows(s2, P2, M2, Z2);
+    if (wact && lane >= 1 && lane <= wz + 1) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        hr[w][lane - 1][0][j] = Z2[j] - M2[j];   // dy 0, dz 0: T2 corner 110
+        hr[w][lane - 1][1][j] = -M1[j] - Z1[j];  // dy 0, dz 1: T1 corner 010
+        hr[w][lane - 1][2][j] = Z1[j] - P1[j];   // dy 1, dz 0: T1 corner 100
+        hr[w][lane - 1][3][j] = -P2[j] - Z2[j];  // dy 1, dz 1: T2 corner 000
+      }
     }
   }
-  // this thread's voxels (in-tile coordinates) and their in-plane phase-map offsets
-  const int nv = (wx + 1) * (wy + 1);
-  int voff[2], vxs[2], vys[2];
+  __syncthreads();
+
+  // ---- z streaming.  Corner plane q sits in buffer U[(q - z0 + 1) % 3] (rows: own,
+  // below; column x -- column x - 1 comes by a lane shift where it is used), the phase
+  // id and isotropic moduli of voxel plane q in PH, LM at the same index.  At step i
+  // (voxel plane p = z0 + i) the buffers hold planes p - 1, p and p + 1 (in flight); once
+  // the stresses are known, plane p - 1's buffer takes the loads of plane p + 2, issued
+  // before this step's stores so that waiting for them later does not wait for the
+  // stores.  The loop is unrolled three times, so no loaded value is ever copied.
+  // byte offsets of this lane's corner in its row and the row below, within a plane
+  // (the grid's real fields stay below 4 GiB: 12 S < 2^31 complex elements per load)
+  const unsigned oo = (unsigned)((y * N1 + x) * (int)sizeof(T)), ob = (unsigned)((ym * N1 + x) * (int)sizeof(T));
+  const unsigned oph = (unsigned)((y * N1 + x) * 2);
+  T U[3][2][3];
+  int PH[3] = {0, 0, 0};
+  cpx<T> LM[3] = {{0, 0}, {0, 0}, {0, 0}};
+  const int plane_bytes = NP * (int)sizeof(T);
+  // corner plane q (q clamped to the segment's last one, so every call loads)
+  auto load = [&](int q, T (&B)[2][3]) {
+    const HZ_GLB T* base = ur + (long long)plane(min(q, z0 + wz)) * NP;
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int v = tid + k * kThreads;
-    vys[k] = v / (wx + 1);
-    vxs[k] = v - vys[k] * (wx + 1);
-    int gx = x0 + vxs[k], gy = y0 + vys[k];
-    while (gx >= N1) gx -= N1;
-    while (gy >= N2) gy -= N2;
-    voff[k] = gy * N1 + gx;
-  }
-  // the fetch of a plane brings its corners and the phase ids of its voxels; the
-  // stiffness entries of the isotropic case follow one step later, so no load sits
-  // on a step's critical path
-  T rg[NL];
-  int rph[2] = {0, 0}, cph[2] = {0, 0};
-  cpx<T> clm[2] = {{0, 0}, {0, 0}};
-  auto fetch = [&](int q) {
-    const int qq = q < 0 ? q + N3 : (q >= N3 ? q - N3 : q);
-    const HZ_GLB T* base = ur + (long long)qq * NP;
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-      if (loff[k] >= 0) rg[k] = base[loff[k]];
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-      if (tid + k * kThreads < nv) rph[k] = ph[(long long)qq * NP + voff[k]];
-  };
-  auto stash = [&](int slot) {
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-      if (loff[k] >= 0) ub[slot][tid + k * kThreads] = rg[k];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      cph[k] = rph[k];
-      if (ISO && tid + k * kThreads < nv) clm[k] = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(C) + cph[k]);
+    for (int j = 0; j < 3; ++j) {
+      const __amdgpu_buffer_rsrc_t r = plane_rsrc((const void*)(base + (long long)j * Nn), plane_bytes);
+      B[0][j] = buf_ld(T(), r, oo);
+      B[1][j] = buf_ld(T(), r, ob);
     }
   };
-  fetch(z0 - 1);
-  stash((z0 + 1) & 1);
-  fetch(z0);
-  stash(z0 & 1);
-  fetch(z0 + 1);
-  T acc[3] = {0, 0, 0};
+  // phase id of voxel (x, y, q), q clamped to the segment's last voxel plane
+  auto phase_at = [&](int q) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc((const void*)(ph + (long long)plane(min(q, z0 + wz)) * NP), 2 * NP);
+    return (int)__builtin_amdgcn_raw_buffer_load_b16(r, (int)oph, 0, 0);
+  };
+  auto moduli = [&](int phase) { return gld(Clm + phase); };
+  // the same issue order as in the loop: planes z0 - 1 and z0, phase ids, moduli,
+  // then plane z0 + 1 last (the one needed latest)
+  load(z0 - 1, U[0]);
+  load(z0, U[1]);
+  __builtin_amdgcn_sched_barrier(0);
+  PH[1] = phase_at(z0);
+  PH[2] = phase_at(z0 + 1);
+  if constexpr (ISO) LM[1] = moduli(PH[1]);
+  __builtin_amdgcn_sched_barrier(0);
+  load(z0 + 1, U[2]);  // wz >= 1
+  T Ap[4][3];  // [dx*2 + dy]: contributions of voxel plane p - 1 to corner plane p - 1
   double sacc[6] = {0, 0, 0, 0, 0, 0};
+  // one z step; returns true after the segment's last voxel plane
+  auto step = [&](const int i, auto bc) -> bool {
+    constexpr int b0 = decltype(bc)::value, b1 = (b0 + 1) % 3, b2 = (b0 + 2) % 3;
+    const int p = z0 + i;
+    const T(&uo0)[3] = U[b0][0];
+    const T(&ub0)[3] = U[b0][1];
+    const T(&uo1)[3] = U[b1][0];
+    const T(&ub1)[3] = U[b1][1];
+    const int phc = PH[b1];
+    const cpx<T> lmc = LM[b1];
+    const T* e0 = lh[w][i];      // column x0 - 1, plane p - 1
+    const T* e1 = lh[w][i + 1];  // plane p
+    T s1[6], s2[6];
+    {
+      T u4[4][3], e[6];  // T1: corners 001, 010, 100, 111
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        u4[0][j] = ub0[j];
+        u4[1][j] = lane_shift<kShr1>(uo0[j], e0[3 + j]);
+        u4[2][j] = lane_shift<kShr1>(ub1[j], e1[j]);
+        u4[3][j] = uo1[j];
+      }
+      stencil_strain_k<T, 0>(u4, e);
+      if constexpr (ISO) constitutive_iso<EIG, T>(lmc.x, lmc.y, Mn, phc, e, s1);
+      else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s1[k] = e[k];  // the strain, until both are known
+      }
+    }
+    {
+      T u4[4][3], e[6];  // T2: corners 000, 011, 101, 110
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        u4[0][j] = lane_shift<kShr1>(ub0[j], e0[j]);
+        u4[1][j] = uo0[j];
+        u4[2][j] = ub1[j];
+        u4[3][j] = lane_shift<kShr1>(uo1[j], e1[3 + j]);
+      }
+      stencil_strain_k<T, 1>(u4, e);
+      if constexpr (ISO) constitutive_iso<EIG, T>(lmc.x, lmc.y, Mn, phc, e, s2);
+      else {
+        const T e1s[6] = {s1[0], s1[1], s1[2], s1[3], s1[4], s1[5]};
+        constitutive_pair<EIG, T>(C + phc * 24, Mn, phc, e1s, e, s1, s2);
+      }
+    }
+    // issue order: moduli of plane p + 1 (needed first), phase ids of plane p + 2,
+    // corners of plane p + 2 (needed last); past the segment's end the loads repeat its
+    // last plane (unused), which keeps the step free of branches around them
+    if constexpr (ISO) LM[b2] = moduli(PH[b2]);
+    __builtin_amdgcn_sched_barrier(0);
+    PH[b0] = phase_at(p + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    load(p + 2, U[b0]);
+    if (i < wz && wact && xact) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sacc[k] += 0.5 * ((double)s1[k] + (double)s2[k]);
+    }
+    T P1[3], M1[3], Z1[3], P2[3], M2[3], Z2[3];
+    stress_rows(s1, P1, M1, Z1);
+    stress_rows(s2, P2, M2, Z2);
+    T X0[3], X1[3];
+    if (i > 0) {
+      // corner plane p - 1 is complete: add the voxel plane p terms (dz = 1); column
+      // x + 1's A10, A11 by a lane shift (lane 63 of a full tile: the halo column)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const T H10 = hr[w][i - 1][0][j] + hr[w][i][1][j];
+        const T H11 = hr[w][i - 1][2][j] + hr[w][i][3][j];
+        const T A10 = Ap[2][j] - (M1[j] + Z1[j]);  // T1 corner 010
+        const T A11 = Ap[3][j] - (P2[j] + Z2[j]);  // T2 corner 000
+        X0[j] = (Ap[0][j] + (P2[j] - Z2[j])) + lane_shift<kShl1>(A10, H10);  // T2 corner 011
+        X1[j] = (Ap[1][j] + (M1[j] - Z1[j])) + lane_shift<kShl1>(A11, H11);  // T1 corner 001
+        xb[i & 1][w][j][lane] = X1[j];
+      }
+    }
+    // voxel plane p's terms of corner plane p (dz = 0)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Ap[0][j] = P1[j] + Z1[j];  // T1 corner 111
+      Ap[1][j] = M2[j] + Z2[j];  // T2 corner 101
+      Ap[2][j] = Z2[j] - M2[j];  // T2 corner 110
+      Ap[3][j] = Z1[j] - P1[j];  // T1 corner 100
+    }
+    __syncthreads();
+    if (i > 0 && wact && xact) {
+      HZ_GLB T* gp = gr + (long long)(p - 1) * NP;
+      if (w + 1 < wy) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          buf_st((T)0.5 * (X0[j] + xb[i & 1][w + 1][j][lane]), plane_rsrc((void*)(gp + (long long)j * Nn), plane_bytes),
+                 oo);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) unsafeAtomicAdd((T*)(gp + (long long)j * Nn + y * N1 + x), (T)0.5 * X0[j]);
+      }
+      if (w == 0) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) unsafeAtomicAdd((T*)(gp + (long long)j * Nn + ym * N1 + x), (T)0.5 * X1[j]);
+      }
+    }
+    return i == wz;
+  };
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
+  using B2 = std::integral_constant<int, 2>;
 #pragma unroll 1
-  for (int p = z0; p <= z0 + wz; ++p) {
-    const int cur = p & 1, prv = cur ^ 1;
-    T g1[3] = {0, 0, 0}, g0[3] = {0, 0, 0};
-    if constexpr (PAIR) {
-      // the 4 corners of tetrahedron k of voxel (vx, vy) of plane p
-      auto corners = [&](auto kc, int vx, int vy, T (&u4)[4][3]) {
-        constexpr int k = decltype(kc)::value;
-        int i = 0;
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-          if (tet_of(o) != k) continue;
-          const int ix = vx + ((o & 1) ? 1 : 0), iy = vy + ((o & 2) ? 1 : 0);
-          const int slot = (o & 4) ? cur : prv;
-#pragma unroll
-          for (int j = 0; j < 3; ++j) u4[i][j] = ub[slot][(j * UY + iy) * UX + ix];
-          ++i;
-        }
-      };
-      // corner (cx, cy) receives sigma^Tk of voxel (cx - o1, cy - o2) for o in Tk;
-      // with w(o) = +-1/2 the sums carry 2 sigma.w and the 1/2 is applied at the store
-      auto gather = [&](auto kc, const T (&sk)[6][VY][VX]) {
-        constexpr int k = decltype(kc)::value;
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-          if (tet_of(o) != k) continue;
-          const int vx = cx + ((o & 1) ? 0 : 1), vy = cy + ((o & 2) ? 0 : 1);
-          auto pm = [](bool plus, T x) { return plus ? x : -x; };
-          const bool p0 = o & 1, p1 = o & 2, p2 = o & 4;
-          const T s0 = sk[0][vy][vx], s1 = sk[1][vy][vx], s2 = sk[2][vy][vx];
-          const T s3 = sk[3][vy][vx], s4 = sk[4][vy][vx], s5 = sk[5][vy][vx];
-          const T f0 = pm(p0, s0) + pm(p1, s5) + pm(p2, s4);
-          const T f1 = pm(p0, s5) + pm(p1, s1) + pm(p2, s3);
-          const T f2 = pm(p0, s4) + pm(p1, s3) + pm(p2, s2);
-          if (o & 4) {
-            g0[0] += f0; g0[1] += f1; g0[2] += f2;
-          } else {
-            g1[0] += f0; g1[1] += f1; g1[2] += f2;
-          }
-        }
-      };
-      using K0 = std::integral_constant<int, 0>;
-      using K1 = std::integral_constant<int, 1>;
-      __syncthreads();  // plane p stashed, the previous gather done with sb
-#pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-        if (tid + sl * kThreads >= nv) continue;
-        const int vy = vys[sl], vx = vxs[sl];
-        T e0[6], e1[6];
-        {
-          T u4[4][3];
-          corners(K0{}, vx, vy, u4);
-          stencil_strain_k<T, 0>(u4, e0);
-        }
-        {
-          T u4[4][3];
-          corners(K1{}, vx, vy, u4);
-          stencil_strain_k<T, 1>(u4, e1);
-        }
-        T s0[6], s1[6];
-        constitutive_pair<EIG, T>(C + cph[sl] * 24, Mn, cph[sl], e0, e1, s0, s1);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          sb[0][c][vy][vx] = s0[c];
-          sb[PAIR ? 1 : 0][c][vy][vx] = s1[c];
-        }
-        if (vx < wx && vy < wy && p < z0 + wz) {
-#pragma unroll
-          for (int c = 0; c < 6; ++c) sacc[c] += 0.5 * ((double)s0[c] + (double)s1[c]);
-        }
-      }
-      __syncthreads();
-      if (own) {
-        gather(K0{}, sb[0]);
-        gather(K1{}, sb[PAIR ? 1 : 0]);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        __syncthreads();  // k = 0: plane p stashed; k = 1: the gather of tetrahedron 0 is done with sb
-        // sigma^Tk of voxel plane p over (wx+1) x (wy+1) voxels
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-          if (tid + sl * kThreads >= nv) continue;
-          const int vy = vys[sl], vx = vxs[sl];
-          T u4[4][3];
-          int i = 0;
-#pragma unroll
-          for (int o = 0; o < 8; ++o) {
-            if (tet_of(o) != k) continue;
-            const int ix = vx + ((o & 1) ? 1 : 0), iy = vy + ((o & 2) ? 1 : 0);
-            const int slot = (o & 4) ? cur : prv;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) u4[i][j] = ub[slot][(j * UY + iy) * UX + ix];
-            ++i;
-          }
-          T out[6];
-          if (k == 0) stencil_sigma_iso_k<T, EIG, 0>(Mn, cph[sl], clm[sl], u4, out);
-          else stencil_sigma_iso_k<T, EIG, 1>(Mn, cph[sl], clm[sl], u4, out);
-#pragma unroll
-          for (int c = 0; c < 6; ++c) sb[0][c][vy][vx] = out[c];
-          if (vx < wx && vy < wy && p < z0 + wz) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) sacc[c] += 0.5 * (double)out[c];
-          }
-        }
-        __syncthreads();
-        if (own) {
-          // corner (cx, cy) receives sigma^Tk of voxel (cx - o1, cy - o2) for o in Tk;
-          // with w(o) = +-1/2 the sums carry 2 sigma.w and the 1/2 is applied at the store
-#pragma unroll
-          for (int o = 0; o < 8; ++o) {
-            if (tet_of(o) != k) continue;
-            const int vx = cx + ((o & 1) ? 0 : 1), vy = cy + ((o & 2) ? 0 : 1);
-            auto pm = [](bool plus, T x) { return plus ? x : -x; };
-            const bool p0 = o & 1, p1 = o & 2, p2 = o & 4;
-            const T s0 = sb[0][0][vy][vx], s1 = sb[0][1][vy][vx], s2 = sb[0][2][vy][vx];
-            const T s3 = sb[0][3][vy][vx], s4 = sb[0][4][vy][vx], s5 = sb[0][5][vy][vx];
-            const T f0 = pm(p0, s0) + pm(p1, s5) + pm(p2, s4);
-            const T f1 = pm(p0, s5) + pm(p1, s1) + pm(p2, s3);
-            const T f2 = pm(p0, s4) + pm(p1, s3) + pm(p2, s2);
-            if (o & 4) {
-              g0[0] += f0; g0[1] += f1; g0[2] += f2;
-            } else {
-              g1[0] += f0; g1[1] += f1; g1[2] += f2;
-            }
-          }
-        }
-      }
-    }
-    if (own) {
-      if (p > z0) {
-        const int at = (p - 1) * NP + (y0 + cy) * N1 + (x0 + cx);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) gr[(long long)j * Nn + at] = (T)0.5 * (acc[j] + g1[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < 3; ++j) acc[j] = g0[j];
-    }
-    // corner plane p+1 goes where plane p-1 was (no longer read), then fetch p+2
-    if (p < z0 + wz) {
-      stash(prv);
-      if (p + 1 < z0 + wz) fetch(p + 2);
-    }
+  for (int i = 0;; i += 3) {
+    if (step(i, B0{})) break;
+    if (step(i + 1, B1{})) break;
+    if (step(i + 2, B2{})) break;
   }
   block_sum<6>(sacc, red);
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     double* pp = d.part_sig + (long long)tile * 6;
 #pragma unroll
     for (int c = 0; c < 6; ++c) pp[c] = sacc[c];
