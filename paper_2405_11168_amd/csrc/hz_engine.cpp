@@ -213,7 +213,10 @@ void Shape::init(int n1, int n2, int n3) {
   sg.N1 = G.N1;
   sg.N2 = G.N2;
   sg.N3 = G.N3;
-  sg.TZ = std::min(kStZ, G.N3);
+  // z segments of kStZ planes where that still leaves about six blocks per CU for one
+  // load (fewer halo planes and per-block set-ups), else half of it
+  const long long tiles_xy = (long long)((G.N1 + kStX - 1) / kStX) * ((G.N2 + kStY - 1) / kStY);
+  sg.TZ = std::min(tiles_xy * ((G.N3 + kStZ - 1) / kStZ) >= 1536 ? kStZ : kStZ / 2, G.N3);
   sg.tx = (G.N1 + kStX - 1) / kStX;
   sg.ty = (G.N2 + kStY - 1) / kStY;
   sg.tz = (G.N3 + sg.TZ - 1) / sg.TZ;

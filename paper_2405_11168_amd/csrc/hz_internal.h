@@ -126,7 +126,7 @@ struct YGeo {
 // stencil tile: 64 corners along x (one per lane of a wave), one corner row per wave
 // along y (kStY = kThreads / 64), and at most kStZ corner planes per block along z
 #ifndef HZ_STZ
-#define HZ_STZ 16
+#define HZ_STZ 32
 #endif
 constexpr int kStX = 64, kStY = kThreads / 64, kStZ = HZ_STZ;
 struct SGeo {
