@@ -81,7 +81,7 @@ typedef struct hz_grid_s* hz_grid;
  *   through the transforms.
  * HZ_SCHEME_STENCIL: strains and corner forces by the 4-corner stencils in real
  *   space, so only the 3 displacement and 3 force components are transformed
- *   (needs N1/2 with a power-of-two factor, see hz_scheme_available).
+ *   (available for every grid the library accepts, see hz_scheme_available).
  * HZ_SCHEME_AUTO: the stencil form where available, else the spectral one. */
 #define HZ_SCHEME_AUTO 0
 #define HZ_SCHEME_SPECTRAL 1
@@ -232,9 +232,10 @@ int hz_effective_stiffness(hz_grid g, const hz_opts* o, double C_eff[36], hz_inf
  * convention u~(q) = exp(i q.(1/2,1/2,1/2)) u(q) (u(q) of eq. FT_u). */
 int hz_get_displacement(hz_grid g, int32_t load, double* out);
 
-/* 1 if the grid's sizes allow the given scheme (HZ_SCHEME_SPECTRAL: always;
- * HZ_SCHEME_STENCIL: N1/2 factors with a power-of-two first radix), 0 if not,
- * negative error code on invalid arguments. */
+/* 1 if the grid's sizes allow the given scheme (HZ_SCHEME_SPECTRAL and
+ * HZ_SCHEME_STENCIL: every grid hz_create_grid accepts, the stencil form's x
+ * transforms taking an odd first radix, or one pass, where N1/2 has no factor 2),
+ * 0 if not, negative error code on invalid arguments. */
 int hz_scheme_available(hz_grid g, int32_t scheme);
 
 /* Reference medium the automatic rule picks for a set of phases: isotropic with

@@ -47,7 +47,7 @@ void check_opts(const hz_opts& o) {
 }
 
 int pick_form(const Shape& sh, int scheme) {
-  if (scheme == HZ_SCHEME_STENCIL && !sh.stencil) fail(HZ_EINVAL, "the stencil scheme needs N1/2 with a power-of-two factor");
+  if (scheme == HZ_SCHEME_STENCIL && !sh.stencil) fail(HZ_EINVAL, "the stencil scheme does not fit this grid's x rows");
   if (scheme == HZ_SCHEME_SPECTRAL || scheme == HZ_SCHEME_STRAIN) return scheme;
   return sh.stencil ? HZ_SCHEME_STENCIL : HZ_SCHEME_SPECTRAL;
 }

@@ -134,22 +134,29 @@ bool make_xplans(int M, Plan& inv, Plan& fwd) {
 // Factorisation of M = N1/2 for the stencil form's separate x transforms: the C2R
 // split sits in the first pass and the R2C merge in the last one, and those passes
 // hold both halves of a pair in registers, so they take the smallest power-of-two
-// radix (the inverse plan starts with it, the forward plan is its reverse).
+// radix, or the smallest odd one where M has no factor 2 (the inverse plan starts
+// with it, the forward plan is its reverse).  A prime M (and M = 1, a radix-1 pass)
+// is one pass that splits and merges alone.
 bool make_split_plans(int M, Plan& inv, Plan& fwd) {
+  if (M == 1) {
+    inv = fwd = plan_of({1}, 1);
+    return true;
+  }
   const Plan p = make_plan(M);
   std::vector<int> v(p.radix, p.radix + p.np);
   auto pow2 = [](int r) { return r == 16 || r == 8 || r == 4 || r == 2; };
   if (v.empty()) return false;
-  if (v.size() == 1) {  // two passes at least
+  if (v.size() == 1) {  // two passes at least where M has a factor 2
     if (v[0] == 16) v = {4, 4};
     else if (v[0] == 8) v = {2, 4};
     else if (v[0] == 4) v = {2, 2};
-    else return false;
   }
   int best = -1;
   for (int i = 0; i < (int)v.size(); ++i)
     if (pow2(v[i]) && (best < 0 || v[i] < v[best])) best = i;
-  if (best < 0) return false;
+  if (best < 0)
+    for (int i = 0; i < (int)v.size(); ++i)
+      if (best < 0 || v[i] < v[best]) best = i;
   const int r = v[best];
   v.erase(v.begin() + best);
   v.insert(v.begin(), r);
@@ -209,7 +216,7 @@ void Shape::init(int n1, int n2, int n3) {
     while (ty3 > 1 && (!x3_fits(ty3) || G.N2 % ty3)) --ty3;
     TY3[d] = x3_fits(ty3) ? ty3 : 0;
   }
-  stencil = xfused && split && TY3[0] > 0 && TY3[1] > 0;
+  stencil = split && TY3[0] > 0 && TY3[1] > 0;
   sg.N1 = G.N1;
   sg.N2 = G.N2;
   sg.N3 = G.N3;

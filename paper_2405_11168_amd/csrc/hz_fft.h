@@ -94,6 +94,10 @@ struct Trig16 {
 // In-register DFT of length R: a[k] <- sum_n a[n] exp(-+2 pi i n k / R)
 template <typename T, int R, bool INV> struct Dft;
 
+template <typename T, bool INV> struct Dft<T, 1, INV> {
+  static __device__ __forceinline__ void run(cpx<T>*) {}
+};
+
 template <typename T, bool INV> struct Dft<T, 2, INV> {
   static __device__ __forceinline__ void run(cpx<T>* a) {
     cpx<T> t = a[0] - a[1];

@@ -98,6 +98,18 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ desc
   xf_load<T, R0, 3>(xg, spec + row0, buf, twl);
   __syncthreads();
   const LdsAcc<T> lds{buf, xg.H1p, 1};
+  // real row (l3, l2) of comp c as M complex values z[n] = x[2n] + i x[2n+1]
+  const int half_n = (xg.N1 / 2) * xg.N2 * xg.N3;
+  const GblAcc<T> out{spec + 3 * xg.S + (long long)row0 * M, half_n, TY, M, 1};
+  if (np == 1) {
+    // one pass (M prime or 1): the split pass left the lines in natural order
+#pragma unroll 1
+    for (int e = threadIdx.x; e < 3 * TY * M; e += kThreads) {
+      const int t = fdiv(e, xg.rM), j = e - t * M;
+      out.put(t, j, lds.get(t, j));
+    }
+    return;
+  }
   int Ns = R0;
 #pragma unroll 1
   for (int p = 1; p < np - 1; ++p) {
@@ -105,9 +117,6 @@ __global__ __launch_bounds__(kThreads) void k_xc2r(const Desc* __restrict__ desc
     __syncthreads();
     Ns *= pi.radix[p];
   }
-  // real row (l3, l2) of comp c as M complex values z[n] = x[2n] + i x[2n+1]
-  const int half_n = (xg.N1 / 2) * xg.N2 * xg.N3;
-  const GblAcc<T> out{spec + 3 * xg.S + (long long)row0 * M, half_n, TY, M, 1};
   pass_any<T, emax<T>(), true>(pi.radix[np - 1], M, Ns, 3 * TY, true, twl, 2, lds, out, false, pi.rLR[np - 1],
                                pi.rNs[np - 1], 0.f);
 }
@@ -139,6 +148,17 @@ __global__ __launch_bounds__(kThreads) void k_xr2c(const Desc* __restrict__ desc
   const LdsAcc<T> lds{buf, xg.H1p, 1};
   const int half_n = (xg.N1 / 2) * xg.N2 * xg.N3;
   const GblAcc<T> in{spec + 6 * xg.S + (long long)row0 * M, half_n, TY, M, 1};
+  if (np == 1) {
+    // one pass (M prime or 1): the merge pass reads the lines in natural order
+#pragma unroll 1
+    for (int e = threadIdx.x; e < 3 * TY * M; e += kThreads) {
+      const int t = fdiv(e, xg.rM), j = e - t * M;
+      lds.put(t, j, in.get(t, j));
+    }
+    __syncthreads();
+    xf_store<T, RL, 3>(xg, spec + 9 * xg.S + row0, buf, twl);
+    return;
+  }
   pass_any<T, emax<T>(), false>(pf.radix[0], M, 1, 3 * TY, true, twl, 2, in, lds, false, pf.rLR[0], pf.rNs[0], 0.f);
   __syncthreads();
   int Ns = pf.radix[0];
@@ -557,6 +577,10 @@ hipError_t launch_xc2r(const Desc* descs, const int* active, int nact, const XGe
     case 8: hipLaunchKernelGGL((k_xc2r<T, 8>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
     case 4: hipLaunchKernelGGL((k_xc2r<T, 4>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
     case 2: hipLaunchKernelGGL((k_xc2r<T, 2>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
+    case 7: hipLaunchKernelGGL((k_xc2r<T, 7>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
+    case 5: hipLaunchKernelGGL((k_xc2r<T, 5>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
+    case 3: hipLaunchKernelGGL((k_xc2r<T, 3>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
+    case 1: hipLaunchKernelGGL((k_xc2r<T, 1>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXi, tw); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -573,6 +597,10 @@ hipError_t launch_xr2c(const Desc* descs, const int* active, int nact, const XGe
     case 8: hipLaunchKernelGGL((k_xr2c<T, 8>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
     case 4: hipLaunchKernelGGL((k_xr2c<T, 4>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
     case 2: hipLaunchKernelGGL((k_xr2c<T, 2>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
+    case 7: hipLaunchKernelGGL((k_xr2c<T, 7>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
+    case 5: hipLaunchKernelGGL((k_xr2c<T, 5>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
+    case 3: hipLaunchKernelGGL((k_xr2c<T, 3>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
+    case 1: hipLaunchKernelGGL((k_xr2c<T, 1>), grid, dim3(kThreads), shm, s, descs, active, xg, *planXf, tw); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -107,6 +107,12 @@ def check_pair(shape, g, r, ref, K, fields=True):
     ((192, 14, 4), 2, 15, "iso", True, 2),
     ((64, 4, 2), 2, 16, "aniso", False, 3),
     ((320, 6, 4), 2, 17, "iso", False, 2),
+    # N1/2 without a factor 2: the stencil form's x transforms split and merge on an odd
+    # radix (15 = 3 then 5, 9 = 3 x 3, 63 = 3, 7, 3) or in one pass (5)
+    ((30, 12, 10), 3, 18, "aniso", False, 4),
+    ((18, 20, 6), 2, 19, "aniso", True, 4),
+    ((126, 8, 6), 2, 20, "iso", False, 3),
+    ((10, 6, 8), 2, 21, "iso", True, 5),
 ])
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
 def test_fp64_iterates_match_oracle(shape, n_phases, seed, kind, voids, K, scheme):
@@ -273,7 +279,8 @@ def test_fp32_fixed_count_matches_oracle_iterate(scheme):
     iterate K, to the 1e-6 relative bound stated for FP32 fields: every FP32 pass rounds
     the fields by a few units of 2^-24 (6e-8), and the scheme is a contraction, so the
     FP32 iterate stays within a small multiple of that of the FP64 one."""
-    for shape, seed, kind, K in (((64, 16, 12), 51, "iso", 12), ((32, 48, 40), 52, "aniso", 10)):
+    for shape, seed, kind, K in (((64, 16, 12), 51, "iso", 12), ((32, 48, 40), 52, "aniso", 10),
+                                 ((30, 12, 10), 53, "aniso", 8), ((14, 8, 28), 54, "iso", 8)):
         ph, C, C0, E = random_problem(shape, 3, seed, kind)
         g = hz.Grid(*shape)
         g.set_material(C, ph)
