@@ -135,12 +135,15 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
   for (int e0 = threadIdx.x; e0 < ne; e0 += CH * kThreads) {
     cpx<T> uv[CH][3];
     cpx<float> rv[CH][3];
+    cpx<double> t2v[CH], t3v[CH];  // e^{-i q2}, e^{-i q3} of the chunk's elements
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
       const int e = e0 + i * kThreads;
       if (e >= ne) break;
       const int h3 = fdiv(e, zg.rTX), col = e - h3 * TX;
       const int o = h3 * N2 + col;
+      t2v[i] = tw2[h2_0 + col];
+      t3v[i] = tw3[h3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         if (!STENCIL && (MODE == 0 || MODE == 2)) uv[i][c] = gld(uin + c * zg.S + o);
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
         continue;
       }
       cpx<double> D1[3], D2[3];
-      symbols(t1, tw2[h2], tw3[h3], D1, D2);
+      symbols(t1, t2v[i], t3v[i], D1, D2);
       // K_il = sum_jk C0_ijkl M_jk,  M_jk = 2 Re(conj(D_j) D_k)
       double Mjk[3][3];
 #pragma unroll
