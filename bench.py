@@ -282,12 +282,15 @@ def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5, s
     loop with Poisson arrivals at load_factor x that rate.  Latency = result
     ready (the server step that retired the request) - arrival time."""
     t0 = time.perf_counter()
-    reqs = [syn.serving_request(i) for i in range(n_req)]
-    grids = []
-    for p in reqs:
+    reqs, grids = [], []
+    for i in range(n_req):
+        p = syn.serving_request(i)
         g = hz.Grid(*p.shape)
         g.set_material(p.C, p.phase)
+        reqs.append(p)
         grids.append(g)
+        if (i + 1) % 250 == 0:
+            print(f"serve: {i + 1} of {n_req} requests generated", file=sys.stderr, flush=True)
     gen_s = time.perf_counter() - t0
     need = [hz.request_bytes(g, hz.HZ_FP32_REFINE, 1) for g in grids]
     arena = min(int(1.05 * sum(need)), 160 << 30)
@@ -331,6 +334,9 @@ def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factor=0.7, seed=5, s
                         lat[i] = t - arrivals[i]
                         res[i] = out
                         del ids[i]
+                        done = n_req - sum(r is None for r in res)
+                        if done % 250 == 0:
+                            print(f"serve: {done} of {n_req} retired", file=sys.stderr, flush=True)
         return lat, res, time.perf_counter() - start
 
     closed_lat, closed_res, makespan = run(np.zeros(n_req))
