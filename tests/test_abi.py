@@ -42,6 +42,27 @@ def test_size_checks():
         assert g.workspace_bytes(hz.HZ_FP64, 1) > 0
 
 
+def test_size_limits_and_both_schemes_on_every_accepted_grid():
+    """Each axis up to the largest 7-smooth even size whose FP64 transform tile fits the
+    64 KB of LDS the transforms use (N1, N3 <= 1008, N2 <= 2016), a load's 12 spectra under
+    2^31 complex elements (700^3 accepted, 720^3 refused); on every accepted grid both
+    forms are available, the stencil form's x transforms splitting on an odd radix, or in
+    one pass, where N1/2 has no factor 2."""
+    lib = hz.lib()
+    h = ctypes.c_void_p()
+    for shape, code in [((1008, 8, 8), hz.HZ_OK), ((1024, 8, 8), _abi.HZ_EINVAL),
+                        ((8, 2016, 8), hz.HZ_OK), ((8, 2048, 8), _abi.HZ_EINVAL),
+                        ((8, 8, 1008), hz.HZ_OK), ((8, 8, 1024), _abi.HZ_EINVAL),
+                        ((700, 700, 700), hz.HZ_OK), ((720, 720, 720), _abi.HZ_EINVAL)]:
+        assert lib.hz_create_grid(*shape, ctypes.byref(h)) == code, shape
+        if code == hz.HZ_OK:
+            lib.hz_destroy_grid(h)
+    for shape in [(2, 4, 6), (6, 10, 12), (10, 6, 8), (14, 8, 28), (18, 20, 6), (30, 12, 10),
+                  (126, 8, 6), (128, 128, 128), (1008, 8, 8), (192, 192, 320)]:
+        g = hz.Grid(*shape)
+        assert g.scheme_available(hz.HZ_SCHEME_SPECTRAL) and g.scheme_available(hz.HZ_SCHEME_STENCIL), shape
+
+
 def test_material_validation():
     g = hz.Grid(4, 4, 6)
     C = np.stack([syn.isotropic_voigt(1, 0.3), syn.isotropic_voigt(2, 0.3)])
