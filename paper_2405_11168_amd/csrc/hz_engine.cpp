@@ -193,10 +193,11 @@ void Shape::init(int n1, int n2, int n3) {
     while (tx > 1 && (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes || G.N2 % tx)) --tx;
     if (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes) fail(HZ_EINVAL, "N3 too large");
     TXz[d] = tx;
-    // y kernel: TX rows of N2 (+ N2 twiddles)
+    // y kernel: TX rows of N2 at the padded pitch (+ N2 twiddles)
+    const int py = lds_pitch(G.N2);
     int ty = std::min(64, tile / G.N2);
-    while (ty > 1 && (ty * G.N2 + G.N2) * csz > kLdsBytes) --ty;
-    if (ty < 1 || G.N2 > tile || (ty * G.N2 + G.N2) * csz > kLdsBytes) fail(HZ_EINVAL, "N2 too large");
+    while (ty > 1 && (ty * py + G.N2) * csz > kLdsBytes) --ty;
+    if (ty < 1 || G.N2 > tile || (ty * py + G.N2) * csz > kLdsBytes) fail(HZ_EINVAL, "N2 too large");
     TXy[d] = ty;
     // x kernel: 6 comps x TY rows x (N1/2+1) in LDS (+ N1 twiddles), TY | N2
     const int hp = (G.N1 / 2) | 1;  // lines hold M = N1/2 values; odd pitch spreads rows over banks

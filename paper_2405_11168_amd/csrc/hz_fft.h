@@ -217,6 +217,20 @@ struct LdsAcc {
   __device__ __forceinline__ void put(int t, int j, cpx<T> v) const { buf[t * sL + j * sJ] = v; }
 };
 
+// LDS lines of unit element stride with one element of padding after every 16: the
+// first Stockham pass writes a butterfly's outputs to consecutive positions, so the
+// lanes of a wave write R elements apart, which without the padding puts them all on
+// the same banks.  Element j of line t sits at t * sL + j + j / 16 (line pitch
+// lds_pitch(L)).
+template <typename T>
+struct LdsPad {
+  static constexpr bool kLds = true;
+  cpx<T>* buf;
+  int sL;  // line pitch, at least lds_pitch(L)
+  __device__ __forceinline__ cpx<T> get(int t, int j) const { return buf[t * sL + j + (j >> 4)]; }
+  __device__ __forceinline__ void put(int t, int j, cpx<T> v) const { buf[t * sL + j + (j >> 4)] = v; }
+};
+
 // global line storage: element (t, j) at p[(t / G) * B + (t % G) * sl + j * sj]
 // (32-bit offsets: a problem's spectra stay below 2^31 elements)
 template <typename T>
@@ -334,9 +348,9 @@ __device__ __forceinline__ void pass_any(int R, int L, int Ns, int lines, bool j
 // run one loop per radix so each keeps its own register allocation.  When dst
 // is LDS the caller synchronises before reading it; when src is LDS the caller
 // synchronised after filling it.
-template <typename T, int EMAX, bool INV, class SRC, class DST>
+template <typename T, int EMAX, bool INV, class LDS, class SRC, class DST>
 __device__ __forceinline__ void fft_lines(const Plan& plan, int lines, float rlines, bool jfast,
-                                          const cpx<T>* __restrict__ tw, int tstride, const LdsAcc<T>& lds,
+                                          const cpx<T>* __restrict__ tw, int tstride, const LDS& lds,
                                           const SRC& src, const DST& dst) {
   const int np = plan.np, L = plan.L;
   if (np == 0) {  // L == 1: copy

@@ -33,6 +33,10 @@ struct Geo {
 // apply the constitutive law: every phase isotropic, and eigenstrains present.
 enum { KIND_ISO = 1, KIND_EIG = 2 };
 
+// Pitch of an LDS line of L complex values stored with one element of padding after
+// every 16 (the layout of the transforms whose lines have unit element stride).
+__host__ __device__ constexpr int lds_pitch(int L) { return L + (L >> 4); }
+
 // Per-problem descriptor.  One launch serves many same-shape problems (load
 // cases of one grid, or requests of a serving group); blockIdx.y picks one.
 struct Desc {
