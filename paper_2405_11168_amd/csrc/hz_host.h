@@ -72,7 +72,7 @@ struct Shape {
   bool xfused = false;  // the x pass runs in its fused form (needs >= 2 radix passes of N1/2)
   int TXz[2]{}, TXy[2]{}, TYx[2]{}, H1p[2]{};  // [0] FP32 kernels, [1] FP64 kernels
   int nbx[2]{}, nbq[2]{};                      // partial-sum blocks of the x and z passes
-  // stencil form (needs the fused x factorisation)
+  // stencil form (every accepted grid, see make_split_plans)
   bool stencil = false;
   int TY3[2]{};  // rows per block of the 3-field x transforms
   SGeo sg{};
