@@ -193,12 +193,15 @@ void Shape::init(int n1, int n2, int n3) {
     while (tx > 1 && (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes || G.N2 % tx)) --tx;
     if (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes) fail(HZ_EINVAL, "N3 too large");
     TXz[d] = tx;
-    // y kernel: TX rows of N2 at the padded pitch (+ N2 twiddles)
-    const int py = lds_pitch(G.N2);
+    // y kernel: TX rows of N2 (+ N2 twiddles), the lines padded after every 16 elements
+    // wherever one padded line fits (the longest lines go unpadded)
+    int py = lds_pitch(G.N2);
+    if ((py + G.N2) * csz > kLdsBytes) py = G.N2;
     int ty = std::min(64, tile / G.N2);
     while (ty > 1 && (ty * py + G.N2) * csz > kLdsBytes) --ty;
     if (ty < 1 || G.N2 > tile || (ty * py + G.N2) * csz > kLdsBytes) fail(HZ_EINVAL, "N2 too large");
     TXy[d] = ty;
+    PYy[d] = py;
     // x kernel: 6 comps x TY rows x (N1/2+1) in LDS (+ N1 twiddles), TY | N2
     const int hp = (G.N1 / 2) | 1;  // lines hold M = N1/2 values; odd pitch spreads rows over banks
     // (the whole-block transforms of the unfused pass, used for output fields, and the
@@ -647,7 +650,7 @@ void pass_front(Engine& e, const Shape& sh, const ShapeTables& tb, const int* ac
     Launch L(e, K_ZEXP, d);
     L.done(launch_zexp<T>(e.d_desc, act, n, zg, sh.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], e.stream), "z expand");
   }
-  const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3, 0};
+  const YGeo yg = sh.ygeo(d, (long long)12 * G.H1 * G.N3, 0);
   Launch L(e, K_YINV, d);
   L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], true, e.stream), "y inverse");
 }
@@ -666,7 +669,7 @@ void pass_front_strain(Engine& e, const Shape& sh, const ShapeTables& tb, const 
                              e.stream),
            "z strain");
   }
-  const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3, 0};
+  const YGeo yg = sh.ygeo(d, (long long)12 * G.H1 * G.N3, 0);
   Launch L(e, K_YINV, d);
   L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], true, e.stream), "y inverse");
 }
@@ -705,7 +708,7 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
   {
-    const YGeo yg{G.N2, sh.TXy[d], (long long)12 * G.H1 * G.N3, 0};
+    const YGeo yg = sh.ygeo(d, (long long)12 * G.H1 * G.N3, 0);
     Launch L(e, K_YFWD, d);
     L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], false, e.stream), "y forward");
   }
@@ -750,7 +753,7 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
   const char* const* tw = d ? tb.tw64 : tb.tw32;
   const ZGeo zg = zgeo(sh, d);
   {
-    const YGeo yg{G.N2, sh.TXy[d], (long long)3 * G.H1 * G.N3, 0, 1};
+    const YGeo yg = sh.ygeo(d, (long long)3 * G.H1 * G.N3, 0, 1);
     Launch L(e, K_YINV3, d);
     L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], true, e.stream), "y inverse");
   }
@@ -775,7 +778,7 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
     L.done(launch_xr2c<T>(e.d_desc, act, n, xg, sh.plans + 7, pf.radix[pf.np - 1], tw[0], e.stream), "x r2c");
   }
   {
-    const YGeo yg{G.N2, sh.TXy[d], (long long)3 * G.H1 * G.N3, 9 * G.S};
+    const YGeo yg = sh.ygeo(d, (long long)3 * G.H1 * G.N3, 9 * G.S);
     Launch L(e, K_YFWD3, d);
     L.done(launch_yline<T>(e.d_desc, act, n, yg, sh.plans + 1, tw[1], false, e.stream), "y forward");
   }

@@ -220,15 +220,15 @@ struct LdsAcc {
 // LDS lines of unit element stride with one element of padding after every 16: the
 // first Stockham pass writes a butterfly's outputs to consecutive positions, so the
 // lanes of a wave write R elements apart, which without the padding puts them all on
-// the same banks.  Element j of line t sits at t * sL + j + j / 16 (line pitch
-// lds_pitch(L)).
+// the same banks.  Element j of line t sits at t * sL + j + (j >> sh): sh = 4 pads
+// (line pitch lds_pitch(L)), sh = 31 leaves the line unpadded (pitch L).
 template <typename T>
 struct LdsPad {
   static constexpr bool kLds = true;
   cpx<T>* buf;
-  int sL;  // line pitch, at least lds_pitch(L)
-  __device__ __forceinline__ cpx<T> get(int t, int j) const { return buf[t * sL + j + (j >> 4)]; }
-  __device__ __forceinline__ void put(int t, int j, cpx<T> v) const { buf[t * sL + j + (j >> 4)] = v; }
+  int sL, sh;
+  __device__ __forceinline__ cpx<T> get(int t, int j) const { return buf[t * sL + j + (j >> sh)]; }
+  __device__ __forceinline__ void put(int t, int j, cpx<T> v) const { buf[t * sL + j + (j >> sh)] = v; }
 };
 
 // global line storage: element (t, j) at p[(t / G) * B + (t % G) * sl + j * sj]

@@ -71,6 +71,10 @@ struct Shape {
                     // stencil form's C2R / R2C x transforms: inverse and forward factorisations
   bool xfused = false;  // the x pass runs in its fused form (needs >= 2 radix passes of N1/2)
   int TXz[2]{}, TXy[2]{}, TYx[2]{}, H1p[2]{};  // [0] FP32 kernels, [1] FP64 kernels
+  int PYy[2]{};                                // LDS line pitch of the y kernel
+  YGeo ygeo(int d, long long nlines, long long off, int from_state = 0) const {
+    return YGeo{geo.N2, TXy[d], nlines, off, from_state, PYy[d], PYy[d] == lds_pitch(geo.N2) ? 4 : 31};
+  }
   int nbx[2]{}, nbq[2]{};                      // partial-sum blocks of the x and z passes
   // stencil form (every accepted grid, see make_split_plans)
   bool stencil = false;

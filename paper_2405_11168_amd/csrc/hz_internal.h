@@ -34,7 +34,7 @@ struct Geo {
 enum { KIND_ISO = 1, KIND_EIG = 2 };
 
 // Pitch of an LDS line of L complex values stored with one element of padding after
-// every 16 (the layout of the transforms whose lines have unit element stride).
+// every 16 (the y transforms' layout wherever such a line fits).
 __host__ __device__ constexpr int lds_pitch(int L) { return L + (L >> 4); }
 
 // Per-problem descriptor.  One launch serves many same-shape problems (load
@@ -115,6 +115,8 @@ struct YGeo {
   long long off;                    // first line's element offset in the spectra (complex elements)
   int from_state;                   // 1: read the lines from the problem's displacement state
                                     // (stencil form), write them to the spectra at off
+  int pitch, pshift;                // LDS line pitch; element j at j + (j >> pshift): 4 pads
+                                    // after every 16 elements, 31 leaves the line unpadded
 };
 
 // Stencil form (same iterates as the Fourier form, eqs. DA1-DA2 in real space).

@@ -198,10 +198,9 @@ __global__ __launch_bounds__(kThreads) void k_yline(const Desc* __restrict__ des
   const long long t0 = (long long)blockIdx.x * yg.TX;
   const int lines = (int)((yg.nlines - t0) < yg.TX ? (yg.nlines - t0) : yg.TX);
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int P = lds_pitch(N2);
-  cpx<T>* twl = buf + yg.TX * P;
+  cpx<T>* twl = buf + yg.TX * yg.pitch;
   stage_table(twl, tw2T, N2);
-  const LdsPad<T> lds{buf, P};
+  const LdsPad<T> lds{buf, yg.pitch, yg.pshift};
   const GblAcc<T> g{glb(reinterpret_cast<cpx<T>*>(d.spec)) + yg.off + t0 * N2, N2, 1, 0, 1};
   if (yg.from_state) {
     void* st = d.src == 1 ? d.u64 : u_slot(d, cur_slot(d));
@@ -460,7 +459,7 @@ hipError_t launch_zexp(const Desc* descs, const int* active, int nact, const ZGe
 template <typename T>
 hipError_t launch_yline(const Desc* descs, const int* active, int nact, const YGeo& yg, const Plan* plan2,
                         const void* tw2T, bool inv, hipStream_t s) {
-  const size_t shm = ((size_t)yg.TX * lds_pitch(yg.N2) + yg.N2) * sizeof(cpx<T>);
+  const size_t shm = ((size_t)yg.TX * yg.pitch + yg.N2) * sizeof(cpx<T>);
   dim3 grid((unsigned)((yg.nlines + yg.TX - 1) / yg.TX), nact);
   if (inv)
     hipLaunchKernelGGL((k_yline<T, true>), grid, dim3(kThreads), shm, s, descs, active, yg, *plan2, (const cpx<T>*)tw2T);
