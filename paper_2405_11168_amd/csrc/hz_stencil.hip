@@ -55,7 +55,8 @@ __global__ __launch_bounds__(kThreads) void k_zconv3(cpx<double>* __restrict__ u
 }
 
 // C2R along x of u (slot 0 -> slot 3 real rows): split + first inverse pass (the
-// smallest power-of-two radix of N1/2), middle passes, last pass to HBM.
+// smallest power-of-two radix of N1/2, else its smallest odd one), middle passes, last
+// pass to HBM; a one-pass plan (N1/2 prime or 1) copies the split pass's lines out.
 // R0: the plan's first radix (one instantiation each, so the register budget is that
 // of the radix actually used)
 template <typename T, int R0>
