@@ -113,6 +113,7 @@ def check_pair(shape, g, r, ref, K, fields=True):
     ((18, 20, 6), 2, 19, "aniso", True, 4),
     ((126, 8, 6), 2, 20, "iso", False, 3),
     ((10, 6, 8), 2, 21, "iso", True, 5),
+    ((126, 96, 80), 3, 22, "aniso", False, 2),   # odd split radix over many tiles (63 = 3, 7, 3)
 ])
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
 def test_fp64_iterates_match_oracle(shape, n_phases, seed, kind, voids, K, scheme):
