@@ -288,14 +288,21 @@ def sphere_contrast(shape, contrast, seed: int = 4, vf: float = 0.25, radius: fl
                    C, C0, loads, tol, {"n_spheres": ns, "vf": avf})
 
 
-def serving_request(i: int, sizes=(32, 48, 64, 96, 128, 160, 192), base_seed: int = 5):
-    """Request i of the serving stream: grid size, microstructure kind, contrast and
-    load drawn from the stream's generator; the microstructure from seed 1000+i."""
+def serving_request_params(i: int, sizes=(32, 48, 64, 96, 128, 160, 192), base_seed: int = 5):
+    """Grid size n, microstructure kind, contrast and load index J of request i of the
+    serving stream (the draws of its generator, without building the microstructure)."""
     rng = np.random.default_rng([base_seed, i])
     n = int(rng.choice(sizes))
     kind = "spheres" if rng.random() < 0.5 else "polycrystal"
     contrast = float(10.0 ** rng.uniform(1.0, 6.0))
     J = int(rng.integers(0, 6))
+    return n, kind, contrast, J
+
+
+def serving_request(i: int, sizes=(32, 48, 64, 96, 128, 160, 192), base_seed: int = 5):
+    """Request i of the serving stream: grid size, microstructure kind, contrast and
+    load drawn from the stream's generator; the microstructure from seed 1000+i."""
+    n, kind, contrast, J = serving_request_params(i, sizes, base_seed)
     seed = 1000 + i
     if kind == "spheres":
         ph, ns, avf = boolean_spheres((n, n, n), n / 16.0, 0.3, seed)

@@ -13,8 +13,9 @@ library.  Each fixture keeps, for one load of one workload:
 
 The GPU tests read the iterate at which an FP64 solve stopped out of
 ``mean_history`` (iterate-matched parity) and compare an FP32+refine solve with
-``mean_sigma``.  At 256^3 one oracle iteration takes tens of seconds on 8
-cores, so the whole set takes about two hours; run it once:
+``mean_sigma``.  ``serving_stream_requests`` keeps the same quantities for ten small
+requests of the serving stream itself.  At 256^3 one oracle iteration takes tens of
+seconds on 8 cores, so the whole set takes about two hours; run it once:
 
     python tests/golden/make_fixtures.py [name ...]
 """
@@ -54,7 +55,54 @@ def _cases():
     }
 
 
+STREAM_PICKS = 10
+
+
+def stream_picks():
+    """Indices of the first STREAM_PICKS requests of the serving stream with n <= 48 and
+    contrast < 10^1.5: small, moderate-contrast requests the oracle converges in seconds."""
+    out, i = [], 0
+    while len(out) < STREAM_PICKS:
+        n, kind, contrast, J = syn.serving_request_params(i)
+        if n <= 48 and contrast < 10 ** 1.5:
+            out.append(i)
+        i += 1
+    return out
+
+
+def make_stream(name="serving_stream_requests"):
+    """Converged oracle runs of requests of the serving stream itself (hz_synth.serving_request)."""
+    reqs = []
+    t0 = time.time()
+    for i in stream_picks():
+        p = syn.serving_request(i)
+        ref = tetra.basic_scheme(p.phase, p.C, p.C0, p.loads[0], tol=TOL_RUN, max_iters=2000, keep_fields=False)
+        assert ref.converged, (i, ref.residual)
+        reqs.append({"index": i, "shape": list(p.shape), "kind": p.info["kind"], "contrast": p.info["contrast"],
+                     "load": p.loads[0].tolist(), "iters": int(ref.iters), "history": ref.history.tolist(),
+                     "mean_history": ref.mean_history.tolist(), "mean_sigma": ref.mean_sigma.tolist()})
+        print(f"  request {i}: {p.shape[0]}^3 {p.info['kind']} contrast {p.info['contrast']:.1f}, "
+              f"{ref.iters} iterations", flush=True)
+    out = {
+        "name": name,
+        "citation": CITATION,
+        "recipe": "hz_synth.serving_request(i) for the first %d requests with n <= 48 and contrast < 10^1.5"
+                  % STREAM_PICKS,
+        "tol_run": TOL_RUN,
+        "requests": reqs,
+        "oracle_wall_s": round(time.time() - t0, 1),
+        "host": f"{platform.processor() or platform.machine()}, {os.cpu_count()} cpus, numpy {np.__version__}",
+        "command": "python tests/golden/make_fixtures.py " + name,
+    }
+    path = os.path.join(HERE, name + ".json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"{name}: {len(reqs)} requests -> {path}", flush=True)
+
+
 def make(name):
+    if name == "serving_stream_requests":
+        return make_stream(name)
     build, recipe, J = _cases()[name]
     p = build()
     E = p.loads[J]
@@ -86,6 +134,6 @@ def make(name):
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or list(_cases())
+    names = sys.argv[1:] or list(_cases()) + ["serving_stream_requests"]
     for n in names:
         make(n)

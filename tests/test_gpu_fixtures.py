@@ -87,3 +87,42 @@ def test_converged_solves_match_stored_oracle_runs(name):
          f"residual {r32.residual[0]:.2e}, <sigma> vs converged {e32:.1e}, {r32.seconds[0]:.3f} s")
     assert r32.status[0] == hz.HZ_OK and r32.residual[0] < 1e-6
     assert e32 < 1e-6
+
+
+def test_serving_stream_requests_match_stored_oracle_runs():
+    """Ten requests of the serving stream itself (hz_synth.serving_request: the first with
+    n <= 48 and contrast < 10^1.5), each submitted in FP64 and FP32+refine to one server
+    on two streams.  FP64 to tol 1e-8 stops at the oracle's first iterate below 1e-8 with
+    <sigma> iterate-matched to 1e-10; FP32+refine to tol 1e-8 is within 1e-6 of the
+    converged <sigma>."""
+    fx = _load("serving_stream_requests")
+    probs, grids = [], []
+    for r in fx["requests"]:
+        p = syn.serving_request(r["index"])
+        assert list(p.shape) == r["shape"] and np.array_equal(p.loads[0], np.array(r["load"]))
+        g = hz.Grid(*p.shape)
+        g.set_material(p.C, p.phase)
+        probs.append(p)
+        grids.append(g)
+    need = sum(hz.request_bytes(g, prec, 1) for g in grids for prec in (hz.HZ_FP64, hz.HZ_FP32_REFINE))
+    srv = hz.Server(int(1.2 * need), max_problems=2 * len(grids) + 4, check_every=8, streams=2)
+    ids = [(srv.submit(g, p.loads, tol=1e-8, C0=p.C0, precision=hz.HZ_FP64, max_iters=4000),
+            srv.submit(g, p.loads, tol=1e-8, C0=p.C0, precision=hz.HZ_FP32_REFINE, max_iters=4000))
+           for g, p in zip(grids, probs)]
+    srv.drain()
+    for r, (i64, i32) in zip(fx["requests"], ids):
+        r64, r32 = srv.result(i64), srv.result(i32)
+        hist = np.array(r["history"])
+        means = np.array(r["mean_history"])
+        conv = np.array(r["mean_sigma"])
+        scale = np.abs(conv).max()
+        k = int(r64.iters[0])
+        k_o = int(np.argmax(hist < 1e-8))
+        em = np.abs(r64.mean_sigma[0] - means[k]).max() / scale
+        e32 = np.abs(r32.mean_sigma[0] - conv).max() / scale
+        _say(f"  request {r['index']} ({r['shape'][0]}^3 {r['kind']}, contrast {r['contrast']:.1f}): FP64 stop "
+             f"iterate {k} (oracle {k_o}), <sigma> {em:.1e}; FP32+refine vs converged {e32:.1e}")
+        assert r64.status[0] == hz.HZ_OK and r32.status[0] == hz.HZ_OK
+        assert k == k_o or (abs(k - k_o) == 1 and abs(hist[min(k, k_o)] / 1e-8 - 1) < 1e-6)
+        assert em < 1e-10
+        assert e32 < 1e-6
