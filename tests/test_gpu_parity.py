@@ -360,6 +360,13 @@ def test_voronoi256_polycrystal_first_iterates():
     _full_size_iterates_both_forms(p, p.loads[3:4], 1, "voronoi256")
 
 
+def test_stiff_endpoint_first_iterates():
+    """The 192 x 192 x 320 sphere cell at contrast 1e8, the stiff end of the contrast sweep
+    (the 256^3 voids test below is the soft end): iterates 0..1 against the oracle."""
+    p = syn.sphere_contrast((192, 192, 320), 1e8)
+    _full_size_iterates_both_forms(p, p.loads[:1], 1, "192x192x320 C=1e8")
+
+
 def test_spheres256_voids_first_iterates():
     """256^3 Boolean spheres to 25% as voids (zero stiffness), the infinite-contrast cell:
     iterates 0..1 against the oracle."""
