@@ -245,7 +245,10 @@ def bounds_margins(np, Ce, C, phase):
     >= 0 for an admissible result."""
     f = np.bincount(phase.ravel(), minlength=len(C)) / phase.size
     CV = np.einsum("p,pij->ij", f, C)
-    CR = np.linalg.inv(np.einsum("p,pij->ij", f, np.linalg.inv(C)))
+    if any(fp > 0 and not np.any(c) for fp, c in zip(f, C)):
+        CR = np.zeros((6, 6))  # a void phase: infinite average compliance, the Reuss bound is 0
+    else:
+        CR = np.linalg.inv(np.einsum("p,pij->ij", f, np.linalg.inv(C)))
     W = np.diag(np.array([1, 1, 1, 2 ** .5, 2 ** .5, 2 ** .5]))  # Mandel = W C W for engineering-shear Voigt
     sym = 0.5 * (Ce + Ce.T)
     top = np.linalg.eigvalsh(W @ sym @ W).max()
@@ -275,6 +278,62 @@ def ceff_leg(hz, np, torch, p, g, tol=1e-8, max_iters=200000):
     out["ceff_rel_diff_fp32r_vs_fp64"] = float(np.abs(res["fp32_refine"] - res["fp64"]).max() /
                                                np.abs(res["fp64"]).max())
     return out
+
+
+def sweep_leg(syn, hz, np, torch, grids, contrasts, cap=40000, stiff_budget=4000):
+    """The contrast sweep on Boolean spheres (R = 8 to vf 0.25, seed 4; matrix E = 1,
+    nu = 0.3; alpha-rule lambda0), load E_xx to tol 1e-6 in FP64 and FP32+refine.
+    Contrasts that converge run to tol under a large cap; stiff ones (C >= 1e4) run a
+    traced budget and report the residual reached and its decay over the last 1000
+    iterations.  At the converging endpoints (voids and C = 10) all six loads solve as
+    one batch and C_eff is reported with its symmetry and bound margins."""
+    rows, ends = [], []
+    for shape in grids:
+        for C in contrasts:
+            p = syn.sphere_contrast(shape, C)
+            g = hz.Grid(*shape)
+            g.set_material(p.C, p.phase)
+            row = {"grid": list(shape), "contrast": C, "n_spheres": p.info["n_spheres"], "vf": round(p.info["vf"], 4)}
+            stiff = C >= 1e4
+            for prec, key in ((hz.HZ_FP64, "fp64"), (hz.HZ_FP32_REFINE, "fp32_refine")):
+                g.bind(prec, 1)
+                torch.cuda.synchronize()
+                r = g.solve(p.loads, tol=1e-6, max_iters=stiff_budget if stiff else cap, precision=prec, C0=p.C0,
+                            trace=stiff, check_every=64)
+                torch.cuda.synchronize()
+                e = {"status": int(r.status[0]), "iters": int(r.iters[0]), "fp64_sweeps": int(r.outer_rounds[0]),
+                     "residual": float(r.residual[0]), "device_s": round(float(r.seconds[0]), 4),
+                     "seconds_to_1e-6": round(float(r.seconds_to_1e6[0]), 4)}
+                if stiff:
+                    h = np.asarray(r.trace_residual[0])
+                    h = h[np.isfinite(h) & (h > 0)]
+                    if len(h) > 1200:
+                        slope = np.polyfit(np.arange(1000), np.log10(h[-1000:]), 1)[0]
+                        e["iters_per_decade_last_1000"] = round(-1.0 / slope, 1) if slope < 0 else None
+                row[key] = e
+            log(f"bench: sweep {row}")
+            rows.append(row)
+            if C in (0.0, 10.0):
+                end = {"grid": list(shape), "contrast": C}
+                res = {}
+                for prec, key in ((hz.HZ_FP64, "fp64"), (hz.HZ_FP32_REFINE, "fp32_refine")):
+                    g.bind(prec, 6)
+                    Ce, r6 = g.effective_stiffness(tol=1e-6, max_iters=cap, precision=prec, C0=p.C0, check_every=64)
+                    torch.cuda.synchronize()
+                    res[key] = Ce
+                    end[key] = {"all_converged": bool(np.all(r6.status == hz.HZ_OK)),
+                                "iters": [int(x) for x in r6.iters], "device_s": round(float(np.max(r6.seconds)), 3),
+                                "C_eff": [[float(f"{x:.7g}") for x in row_] for row_ in Ce],
+                                **bounds_margins(np, Ce, p.C, p.phase)}
+                end["ceff_rel_diff_fp32r_vs_fp64"] = float(np.abs(res["fp32_refine"] - res["fp64"]).max() /
+                                                           np.abs(res["fp64"]).max())
+                log(f"bench: sweep endpoint {end}")
+                ends.append(end)
+            del g
+            torch.cuda.empty_cache()
+    return {"workload": "Boolean spheres R 8 to vf 0.25 (seed 4), matrix E 1 nu 0.3, alpha-rule lambda0, "
+                        "E_xx to tol 1e-6; six loads at C = 0 and 10",
+            "rows": rows, "endpoints": ends}
 
 
 def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factors=(0.7,), seed=5, streams=1):
@@ -497,7 +556,8 @@ def headline(a, hz, np, torch, p, g, copy_gbps):
     }
 
 
-LEGS = ("iter", "ceff", "full", "ttt", "serve", "cpu")
+LEGS = ("iter", "ceff", "full", "ttt", "serve", "cpu", "sweep")
+DEFAULT_LEGS = ("iter", "ceff", "full", "ttt", "serve", "cpu")
 FULL = ("voronoi256", "spheres192x192x320")
 
 
@@ -507,7 +567,7 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--legs", default=",".join(LEGS),
+    ap.add_argument("--legs", default=",".join(DEFAULT_LEGS),
                     help="legs to run, of " + ",".join(LEGS) + " (the JSON line carries the headline value "
                          "only with 'iter')")
     ap.add_argument("--full", default=",".join(FULL), help="full-size workloads, of " + ",".join(FULL))
@@ -522,6 +582,9 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=4, help="streams the server spreads its groups over")
     ap.add_argument("--serve-loads", default="0.7",
                     help="open-loop load factors (x the closed-loop rate), comma separated; the first is reported")
+    ap.add_argument("--sweep-grids", default="256x256x256,192x192x320", help="grids of the contrast sweep")
+    ap.add_argument("--sweep-contrasts", default="0,1e-4,1e-2,10,1e2,1e3,1e4,1e6,1e8",
+                    help="inclusion-to-matrix stiffness ratios of the contrast sweep")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
     a = ap.parse_args()
@@ -605,6 +668,9 @@ def main():
         out["time_to_1e-6"] = time_to_tol(hz, np, torch, poly, gp)
         log(f"bench: ttt {out['time_to_1e-6']}")
     del gp
+    if "sweep" in legs:
+        grids = [tuple(int(v) for v in t.split("x")) for t in a.sweep_grids.split(",")]
+        out["contrast_sweep"] = sweep_leg(syn, hz, np, torch, grids, [float(c) for c in a.sweep_contrasts.split(",")])
     if "serve" in legs:
         log(f"bench: serving leg ({a.serve_n} requests)")
         out["serving"] = serving_leg(syn, hz, np, torch, a.serve_n, a.serve_max_iters, streams=a.serve_streams,
