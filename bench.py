@@ -331,9 +331,26 @@ def sweep_leg(syn, hz, np, torch, grids, contrasts, cap=40000, stiff_budget=4000
                 ends.append(end)
             del g
             torch.cuda.empty_cache()
+    # the isolated inclusion of the contrast study: FP64 iterations to 1e-10, and to 1e-6 in
+    # FP64 and FP32+refine where FP64 rounding floors the residual above 1e-10
+    iso_rows = []
+    for C in (0.0, 1e-6, 1e-3, 0.1, 10.0, 1e2, 1e3, 1e4, 1e6, 1e8):
+        p = syn.isolated_sphere(C)
+        g = hz.Grid(*p.shape)
+        g.set_material(p.C, p.phase)
+        row = {"contrast": C, "vf": round(p.info["vf"], 4)}
+        for prec, tol, key in ((hz.HZ_FP64, 1e-10, "fp64_1e-10"), (hz.HZ_FP64, 1e-6, "fp64_1e-6"),
+                               (hz.HZ_FP32_REFINE, 1e-6, "fp32_refine_1e-6")):
+            g.bind(prec, 1)
+            r = g.solve(p.loads, tol=tol, max_iters=20000, precision=prec, C0=p.C0, check_every=16)
+            row[key] = {"status": int(r.status[0]), "iters": int(r.iters[0]), "residual": float(r.residual[0])}
+        log(f"bench: sweep isolated {row}")
+        iso_rows.append(row)
+        del g
     return {"workload": "Boolean spheres R 8 to vf 0.25 (seed 4), matrix E 1 nu 0.3, alpha-rule lambda0, "
-                        "E_xx to tol 1e-6; six loads at C = 0 and 10",
-            "rows": rows, "endpoints": ends}
+                        "E_xx to tol 1e-6; six loads at C = 0 and 10; the isolated sphere of hz_synth.isolated_sphere "
+                        "(48^3, R = 0.4 N, nu 0.125)",
+            "rows": rows, "endpoints": ends, "isolated": iso_rows}
 
 
 def serving_leg(syn, hz, np, torch, n_req, max_iters, load_factors=(0.7,), seed=5, streams=1):
@@ -669,7 +686,7 @@ def main():
         log(f"bench: ttt {out['time_to_1e-6']}")
     del gp
     if "sweep" in legs:
-        grids = [tuple(int(v) for v in t.split("x")) for t in a.sweep_grids.split(",")]
+        grids = [tuple(int(v) for v in t.split("x")) for t in a.sweep_grids.split(",") if t]
         out["contrast_sweep"] = sweep_leg(syn, hz, np, torch, grids, [float(c) for c in a.sweep_contrasts.split(",")])
     if "serve" in legs:
         log(f"bench: serving leg ({a.serve_n} requests)")

@@ -288,6 +288,21 @@ def sphere_contrast(shape, contrast, seed: int = 4, vf: float = 0.25, radius: fl
                    C, C0, loads, tol, {"n_spheres": ns, "vf": avf})
 
 
+def isolated_sphere(contrast: float, n: int = 48, radius_frac: float = 0.4, nu: float = 0.125) -> Problem:
+    """The contrast study's isolated inclusion (Sec. 3.4): one sphere of radius
+    radius_frac * n centred in an n^3 cell (voxel-centre coordinates, |r - c| <= R),
+    matrix E = 1, inclusion E = contrast (0: a void), both with Poisson ratio nu,
+    the alpha-rule reference medium, load E_xx."""
+    c = n / 2.0 - 0.5
+    l = np.arange(n) - c
+    d2 = l[:, None, None] ** 2 + l[None, :, None] ** 2 + l[None, None, :] ** 2
+    ph = (d2 <= (radius_frac * n) ** 2).astype(np.uint16)
+    C = np.stack([isotropic_voigt(1.0, nu), isotropic_voigt(contrast, nu)])
+    C0 = ref_alpha_rule(1.0, contrast, nu)
+    return Problem(f"isolated{n}_c{contrast:g}", (n, n, n), ph, C, C0, np.array([unit_load(0)]), 1e-10,
+                   {"contrast": contrast, "vf": float(ph.mean())})
+
+
 def serving_request_params(i: int, sizes=(32, 48, 64, 96, 128, 160, 192), base_seed: int = 5):
     """Grid size n, microstructure kind, contrast and load index J of request i of the
     serving stream (the draws of its generator, without building the microstructure)."""

@@ -64,8 +64,9 @@ extern "C" {
                                 reference medium is not positive definite                */
 #define HZ_EWORKSPACE (-5)   /* workspace not bound or too small                           */
 #define HZ_EHIP (-6)         /* a HIP runtime call failed                                  */
-#define HZ_EDIVERGED (-7)    /* residual became NaN/Inf or grew by 1e3 (reference medium
-                                too soft)                                                  */
+#define HZ_EDIVERGED (-7)    /* residual became NaN/Inf, eps grew by 1e3, or the residual
+                                norm grew back above its first value and 10 times its
+                                smallest (reference medium too soft)                      */
 
 typedef struct hz_grid_s* hz_grid;
 

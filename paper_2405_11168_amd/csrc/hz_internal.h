@@ -97,6 +97,7 @@ enum St {
                      // applied strain, zero in a correction round, or under applied stress
                      // the iterate of the loop on the mean strain (updated on the device)
   ST_K1E6 = 22,      // FP64 iterations: first iterate k with eps_k < 1e-6 in this state, or -1
+  ST_L2_FIRST = 23,  // FP64 iterations: the residual norm L2 of the state's first iterate (watchdog)
 };
 constexpr int kStatusLen = 24;
 

@@ -328,7 +328,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
   for (int c = 0; c < 6; ++c) s[ST_MEAN + c] = m[c];
   s[ST_L2SQ] = v[6];
   s[ST_NORM] = nrm;
-  if (k == 0) s[ST_FIRST_ERR] = err;
+  if (k == 0) {
+    s[ST_FIRST_ERR] = err;
+    s[ST_L2_FIRST] = L2;
+  }
   s[ST_K] = k + 1;
   if (fmode == 1) {
     // a sweep measures once; the host decides what follows
@@ -367,13 +370,16 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Desc* __restrict__ 
     conv = conv && dm <= d.tol * d.sref;
   }
   const bool stop = d.fixed_iters >= 0 ? (k >= d.fixed_iters) : conv;
-  // watchdog: NaN/Inf, growth to 1e3 times the first residual, or a residual back above
-  // the first one and 10 times the smallest seen (the iterates run away while <sigma>
-  // grows with them, so eps alone grows only slowly)
-  const double best = k == 0 ? err : fmin(s[ST_BEST], err);
+  // watchdog: NaN/Inf, eps grown to 1e3 times its first value, or the residual norm L2
+  // back above its first value and 10 times the smallest seen.  Iterates that run away
+  // (a reference medium too soft for the basic scheme) make L2 grow geometrically while
+  // <sigma> grows with them, so eps alone grows only slowly; with stiff inclusions eps
+  // can rise transiently by tens of times because <sigma> falls from the Voigt average
+  // by up to the contrast, while L2 only decreases, so the rule reads L2, not eps.
+  const double best = k == 0 ? L2 : fmin(s[ST_BEST], L2);
   s[ST_BEST] = best;
   const bool bad = !(err == err) || isinf(err) ||
-                   (k > 0 && (err > 1e3 * s[ST_FIRST_ERR] || (err > s[ST_FIRST_ERR] && err > 10.0 * best)));
+                   (k > 0 && (err > 1e3 * s[ST_FIRST_ERR] || (L2 > s[ST_L2_FIRST] && L2 > 10.0 * best)));
   if (stop || bad || k >= d.max_iters) {
     s[ST_DONE] = bad ? 3.0 : (stop ? 1.0 : 2.0);
     s[ST_ITERS] = k;
