@@ -114,6 +114,7 @@ def check_pair(shape, g, r, ref, K, fields=True):
     ((126, 8, 6), 2, 20, "iso", False, 3),
     ((10, 6, 8), 2, 21, "iso", True, 5),
     ((126, 96, 80), 3, 22, "aniso", False, 2),   # odd split radix over many tiles (63 = 3, 7, 3)
+    ((8, 2016, 8), 2, 23, "iso", False, 2),      # longest y lines: FP64 lines unpadded in LDS
 ])
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
 def test_fp64_iterates_match_oracle(shape, n_phases, seed, kind, voids, K, scheme):
