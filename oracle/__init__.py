@@ -19,6 +19,10 @@ paper by eye:
 * ``dense``    -- the plain definition: direct minimisation of the collapsed
                   energy of eq. Elast_energy on tiny grids.
 * ``laminate`` -- closed-form effective response of an axis-aligned laminate.
+* ``comparison`` -- the comparison discretisations of Sec. 3.2 and Appendix B
+                  (Willot's rotated scheme, eq. Dq_rotated, and the
+                  continuous-frequency operator of Moulinec-Suquet) as
+                  displacement-based basic schemes with one strain field.
 * ``voigt``    -- Voigt <-> tensor bookkeeping.
 
 Pins (see tests/test_oracle_*.py) tie each part to something other than
