@@ -102,6 +102,29 @@ typedef struct hz_grid_s* hz_grid;
 #define HZ_LOAD_STRAIN 0
 #define HZ_LOAD_STRESS 1
 
+/* Discretisation of the gradient (the Green operator).
+ * HZ_GREEN_TETRA: the paper's tetrahedral stencil (eqs. Dq, DA1-DA2, Green_tensor).
+ * The two others are the comparison discretisations of Sec. 3.2 and Appendix B: one
+ * strain field per voxel, eps = Ebar + D (x)_s u, the inverse displacement Green
+ * function conj(D).lambda0.D (eq. inverse_displacement_Green_function_rotated), the
+ * equilibrium residual r = sigma(q).conj(D) and the update u <- u - Omega.r; the
+ * stop measure is eps_k = ||r|| / ||<sigma>|| (eq. tolerance for one strain field).
+ * HZ_GREEN_ROTATED: Willot's rotated scheme, D of eq. Dq_rotated (differences over the
+ *   8 corners of a voxel); Omega := 0 where D vanishes: q = 0 and every q with two
+ *   components equal to pi (Willot's recipe, Sec. 3.2).
+ * HZ_GREEN_CONTINUOUS: the continuous-frequency gradient of Moulinec-Suquet,
+ *   D = i xi(q) with xi = 2 pi h~ / N on the representative h~ in (-N/2, N/2); at the
+ *   highest frequency of an even axis xi = 0, so the strain stays real (the paper's
+ *   runs use Moulinec-Suquet's strain-based recipe there instead, which has no
+ *   displacement form); Omega := 0 where xi = 0.  Needs N3 <= 680.
+ * Both need HZ_FP64 and the spectral scheme (HZ_SCHEME_AUTO selects it); hz_solve,
+ * hz_solve_static and hz_effective_stiffness only (not served).  hz_get_displacement
+ * then returns exp(i (q1 + q2 + q3)) u(q) for u(q) of eq. Dq_rotated (rotated), and
+ * u(q) itself (continuous). */
+#define HZ_GREEN_TETRA 0
+#define HZ_GREEN_ROTATED 1
+#define HZ_GREEN_CONTINUOUS 2
+
 typedef struct {
   double tol;               /* stop at the first iterate k with eps_k < tol (eq. tolerance)   */
   int32_t max_iters;        /* cap on updates, <= 1000000 (<= 4096 with a trace): FP64 updates,
@@ -135,6 +158,7 @@ typedef struct {
   int32_t fields_on_device; /* 0: eps_out / sig_out of hz_solve are host arrays; 1: device
                                arrays (caller-owned, 8-byte aligned), written on the bound
                                stream before hz_solve returns                                  */
+  int32_t green;            /* HZ_GREEN_TETRA, HZ_GREEN_ROTATED or HZ_GREEN_CONTINUOUS           */
 } hz_opts;
 
 typedef struct {
@@ -155,7 +179,7 @@ typedef struct {
 
 /* Fill *o with defaults: tol 1e-8, max_iters 2000, HZ_FP64, automatic reference,
  * fixed_iters -1, check_every 8, no traces, inner_rho 1e-3, inner_max 400,
- * HZ_SCHEME_AUTO, HZ_LOAD_STRAIN, no initial guess, host field outputs. */
+ * HZ_SCHEME_AUTO, HZ_LOAD_STRAIN, no initial guess, host field outputs, HZ_GREEN_TETRA. */
 void hz_default_opts(hz_opts* o);
 
 /* Create a grid handle for an n1 x n2 x n3 periodic cell (Sec. 2.1).

@@ -16,9 +16,10 @@ import numpy as np
 from . import _abi
 from ._abi import (HZ_EDIVERGED, HZ_FP32_REFINE, HZ_FP64, HZ_LOAD_STRAIN, HZ_LOAD_STRESS, HZ_NOT_CONVERGED, HZ_OK,
                    HZ_PENDING, HZ_SCHEME_AUTO, HZ_SCHEME_SPECTRAL, HZ_SCHEME_STENCIL, HZ_SCHEME_STRAIN,
+                   HZ_GREEN_TETRA, HZ_GREEN_ROTATED, HZ_GREEN_CONTINUOUS,
                    HZ_STAGNATED, HzError, check, hz_info, hz_opts)
 
-__all__ = ["Grid", "Server", "SolveResult", "HZ_FP64", "HZ_FP32_REFINE", "HZ_LOAD_STRAIN", "HZ_LOAD_STRESS", "HzError",
+__all__ = ["Grid", "Server", "SolveResult", "HZ_GREEN_TETRA", "HZ_GREEN_ROTATED", "HZ_GREEN_CONTINUOUS", "HZ_FP64", "HZ_FP32_REFINE", "HZ_LOAD_STRAIN", "HZ_LOAD_STRESS", "HzError",
            "reference_medium", "lib"]
 
 
@@ -164,10 +165,11 @@ class Grid:
 
     # -- solve -----------------------------------------------------------------
     def _prepare(self, nl, tol, max_iters, precision, C0, fixed_iters, trace, check_every, inner_rho, inner_max,
-                 scheme, loading, u_init, Ebar_init):
+                 scheme, loading, u_init, Ebar_init, green=HZ_GREEN_TETRA):
         """Options struct and the host arrays it points to (kept alive by the caller)."""
         self._ensure(precision, 2 * nl if scheme == HZ_SCHEME_STRAIN else nl)
         o = _opts(tol, max_iters, precision, C0, fixed_iters, check_every, inner_rho, inner_max, scheme, loading)
+        o.green = green
         T = (fixed_iters if fixed_iters >= 0 else max_iters) + 1
         keep = {}
         if trace:
@@ -188,18 +190,20 @@ class Grid:
     def solve(self, E, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1,
               fields=False, trace=False, check_every=8, inner_rho=1e-3, inner_max=400,
               scheme=HZ_SCHEME_AUTO, loading=HZ_LOAD_STRAIN, u_init=None, Ebar_init=None,
-              fields_on_device=False) -> SolveResult:
+              fields_on_device=False, green=HZ_GREEN_TETRA) -> SolveResult:
         """E: [n_loads, 6] applied mean strains, or applied stresses with loading=HZ_LOAD_STRESS.
         u_init: optional [n_loads, 3, N1/2+1, N3, N2] complex displacement of iterate 0 (as
         returned by displacement()); Ebar_init: optional [n_loads, 6] mean strain of iterate 0
         under applied stress.  Together they resume a solve from a checkpoint.
+        green: HZ_GREEN_TETRA (the paper's scheme) or a comparison operator,
+        HZ_GREEN_ROTATED / HZ_GREEN_CONTINUOUS (FP64, spectral scheme).
         fields=True returns eps, sigma [n_loads, 6, N3, N2, N1] as numpy arrays, or with
         fields_on_device=True as float64 torch tensors on the workspace's device, written
         there by the library (no host round trip)."""
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
         nl = E.shape[0]
         o, keep = self._prepare(nl, tol, max_iters, precision, C0, fixed_iters, trace, check_every, inner_rho,
-                                inner_max, scheme, loading, u_init, Ebar_init)
+                                inner_max, scheme, loading, u_init, Ebar_init, green)
         sm = np.zeros((nl, 6))
         infos = (hz_info * nl)()
         n1, n2, n3 = self.shape
@@ -221,12 +225,13 @@ class Grid:
         return _result(sm, infos, rc, trace_residual=keep.get("tr"), trace_mean=keep.get("tm"), eps=eps, sigma=sig)
 
     def effective_stiffness(self, tol=1e-8, max_iters=2000, precision=HZ_FP64, C0=None, fixed_iters=-1,
-                            trace=False, check_every=8, inner_rho=1e-3, inner_max=400, scheme=HZ_SCHEME_AUTO):
+                            trace=False, check_every=8, inner_rho=1e-3, inner_max=400, scheme=HZ_SCHEME_AUTO,
+                            green=HZ_GREEN_TETRA):
         """C_eff (6x6 Voigt) by hz_effective_stiffness: column J = <sigma> of the unit load
         gamma_J = 1, the six loads solved as one batch.  Returns (C_eff, SolveResult of the
         six loads in the order J = 0..5)."""
         o, keep = self._prepare(6, tol, max_iters, precision, C0, fixed_iters, trace, check_every, inner_rho,
-                                inner_max, scheme, HZ_LOAD_STRAIN, None, None)
+                                inner_max, scheme, HZ_LOAD_STRAIN, None, None, green)
         Ce = np.zeros(36)
         infos = (hz_info * 6)()
         rc = _outcome(lib().hz_effective_stiffness(self._h, ctypes.byref(o), _dptr(Ce), infos))

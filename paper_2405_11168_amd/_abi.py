@@ -21,6 +21,10 @@ HZ_EDIVERGED = -7
 HZ_FP64 = 0
 HZ_FP32_REFINE = 1
 
+HZ_GREEN_TETRA = 0
+HZ_GREEN_ROTATED = 1
+HZ_GREEN_CONTINUOUS = 2
+
 HZ_SCHEME_AUTO = 0
 HZ_SCHEME_SPECTRAL = 1
 HZ_SCHEME_STENCIL = 2
@@ -48,6 +52,7 @@ class hz_opts(ctypes.Structure):
         ("u_init", POINTER(c_double)),
         ("Ebar_init", POINTER(c_double)),
         ("fields_on_device", c_int32),
+        ("green", c_int32),
     ]
 
 

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhz.so")
-SOURCES = ["hz_kernels.hip", "hz_zcon.hip", "hz_stencil.hip", "hz_engine.cpp", "hz_api.cpp"]
+SOURCES = ["hz_kernels.hip", "hz_zcon.hip", "hz_stencil.hip", "hz_green.hip", "hz_engine.cpp", "hz_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -44,7 +44,15 @@ void check_opts(const hz_opts& o) {
   if (o.loading == HZ_LOAD_STRESS && o.precision != HZ_FP64) fail(HZ_EINVAL, "applied stress needs HZ_FP64");
   if ((o.u_init || o.Ebar_init) && (o.precision != HZ_FP64 || o.scheme == HZ_SCHEME_STRAIN))
     fail(HZ_EINVAL, "an initial guess needs HZ_FP64 and the spectral or stencil scheme");
+  if (o.green < HZ_GREEN_TETRA || o.green > HZ_GREEN_CONTINUOUS) fail(HZ_EINVAL, "unknown Green operator");
+  if (o.green != HZ_GREEN_TETRA && o.precision != HZ_FP64)
+    fail(HZ_EINVAL, "the comparison Green operators need HZ_FP64");
+  if (o.green != HZ_GREEN_TETRA && o.scheme != HZ_SCHEME_AUTO && o.scheme != HZ_SCHEME_SPECTRAL)
+    fail(HZ_EINVAL, "the comparison Green operators run in the spectral scheme");
 }
+static_assert(HZ_GREEN_TETRA == GREEN_TETRA && HZ_GREEN_ROTATED == GREEN_ROTATED &&
+                  HZ_GREEN_CONTINUOUS == GREEN_CONTINUOUS,
+              "Green operator ids");
 
 int pick_form(const Shape& sh, int scheme) {
   if (scheme == HZ_SCHEME_STENCIL && !sh.stencil) fail(HZ_EINVAL, "the stencil scheme does not fit this grid's x rows");
@@ -66,7 +74,10 @@ void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, cons
   p.shape = sh;
   p.tab = tab;
   p.prec = o.precision;
-  p.form = pick_form(*sh, o.scheme);
+  p.form = o.green != HZ_GREEN_TETRA ? HZ_SCHEME_SPECTRAL : pick_form(*sh, o.scheme);
+  p.green = o.green;
+  if (o.green == HZ_GREEN_CONTINUOUS && sh->subc == 0)
+    fail(HZ_EINVAL, "N3 too large for the continuous-frequency operator's z kernels");
   p.loading = o.loading;
   for (int c = 0; c < 6; ++c) p.E[c] = E[c];
   if (o.loading == HZ_LOAD_STRESS && o.Ebar_init) {
@@ -108,6 +119,7 @@ void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, cons
   d.trace = b.trace;
   d.tau64 = mt.tau64;
   d.tau32 = mt.tau32;
+  d.green = o.green;
   d.loading = o.loading;
   if (o.loading == HZ_LOAD_STRESS) {
     auto frob = [](const double* t) {
@@ -530,6 +542,7 @@ void hz_default_opts(hz_opts* o) {
   o->inner_max = 400;
   o->scheme = HZ_SCHEME_AUTO;
   o->loading = HZ_LOAD_STRAIN;
+  o->green = HZ_GREEN_TETRA;
 }
 
 const char* hz_last_error(void) { return g_err.c_str(); }
@@ -806,6 +819,7 @@ int hz_server_submit(hz_server s, hz_grid g, int32_t n_loads, const double* E, c
   pick_form(g->shape, o->scheme);
   if (o->fixed_iters >= 0) fail(HZ_EINVAL, "fixed_iters is not served");
   if (o->scheme == HZ_SCHEME_STRAIN) fail(HZ_EINVAL, "the strain-based scheme is not served (hz_solve only)");
+  if (o->green != HZ_GREEN_TETRA) fail(HZ_EINVAL, "the comparison Green operators are not served (hz_solve only)");
   if (o->u_init || o->Ebar_init) fail(HZ_EINVAL, "initial guesses are not served (hz_solve only)");
   check_loads(E, n_loads);
   if (n_loads > s->max_problems) fail(HZ_EWORKSPACE, "more loads than the server has slots");

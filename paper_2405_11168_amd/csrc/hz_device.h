@@ -117,6 +117,17 @@ __device__ __forceinline__ void affine_symbols(cpx<double> t1, cpx<double> t2, c
   b2[0] = P; b2[1] = P; b2[2] = mS;
 }
 
+// The rotated comparison operator (eq. Dq_rotated) is the mean of the two tetrahedral
+// gradients, with the same half-voxel phase: D~rot = (D~ + D~2)/2 for both strain
+// fields.  Applied to symbol or affine coefficients of T1 (a) and T2 (b) in place.
+__device__ __forceinline__ void rotated_mean(cpx<double>* a, cpx<double>* b) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    a[c] = scale(a[c] + b[c], 0.5);
+    b[c] = a[c];
+  }
+}
+
 // A wave-uniform value moved into scalar registers.
 __device__ __forceinline__ float uniform(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));

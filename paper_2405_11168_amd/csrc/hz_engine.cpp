@@ -193,6 +193,16 @@ void Shape::init(int n1, int n2, int n3) {
     while (tx > 1 && (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes || G.N2 % tx)) --tx;
     if (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes) fail(HZ_EINVAL, "N3 too large");
     TXz[d] = tx;
+    if (d) {
+      // continuous operator: 6 lines per column, the largest divisor of tx that fits
+      subc = 0;
+      for (int s = tx; s >= 1; --s)
+        if (tx % s == 0 && 6 * s * G.N3 <= tile && (6 * s * G.N3 + G.N3) * csz <= kLdsBytes) {
+          subc = s;
+          break;
+        }
+      rsubc6 = subc ? recip(6 * subc) : 0.f;
+    }
     // y kernel: TX rows of N2 (+ N2 twiddles), the lines padded after every 16 elements
     // wherever one padded line fits (the longest lines go unpadded)
     int py = lds_pitch(G.N2);
@@ -639,16 +649,22 @@ ZGeo zgeo(const Shape& sh, int d) {
   return ZGeo{G.N1, G.N2, G.N3, G.H1, TX, G.N2 / TX, recip(TX), recip(3 * TX), recip(G.N2 / TX), G.S};
 }
 
-// P1 (expand + inverse z) and P2 (inverse y)
+// P1 (expand + inverse z) and P2 (inverse y); the continuous-frequency operator has
+// z kernels of its own (FP64), the rotated one shares the tetrahedral kernels
 template <typename T>
-void pass_front(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n) {
+void pass_front(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int green) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
   const ZGeo zg = zgeo(sh, d);
   {
     Launch L(e, K_ZEXP, d);
-    L.done(launch_zexp<T>(e.d_desc, act, n, zg, sh.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], e.stream), "z expand");
+    if (green == GREEN_CONTINUOUS)
+      L.done(launch_zexp_cont(e.d_desc, act, n, zg, sh.subc, sh.rsubc6, sh.plans + 2, tb.tw64[2], e.stream),
+             "z expand");
+    else
+      L.done(launch_zexp<T>(e.d_desc, act, n, zg, sh.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], e.stream),
+             "z expand");
   }
   const YGeo yg = sh.ygeo(d, (long long)12 * G.H1 * G.N3, 0);
   Launch L(e, K_YINV, d);
@@ -703,7 +719,7 @@ void pass_x(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, i
 
 // P4 (forward y), P5 (forward z + contraction + update) and the stop rule
 template <typename T>
-void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int c0) {
+void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, int c0, int green) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
   const char* const* tw = d ? tb.tw64 : tb.tw32;
@@ -715,9 +731,13 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
   {
     const ZGeo zg = zgeo(sh, d);
     Launch L(e, K_ZCON, d);
-    L.done(launch_zcon<T>(e.d_desc, act, n, false, c0, zg, sh.plans + 2, tw[2], tb.tw64[0], tb.tw64[1], tb.tw64[2],
-                          e.stream),
-           "z contract");
+    if (green == GREEN_CONTINUOUS)
+      L.done(launch_zcon_cont(e.d_desc, act, n, zg, sh.subc, sh.rsubc6, sh.plans + 2, tb.tw64[2], e.stream),
+             "z contract");
+    else
+      L.done(launch_zcon<T>(e.d_desc, act, n, false, c0, zg, sh.plans + 2, tw[2], tb.tw64[0], tb.tw64[1],
+                            tb.tw64[2], e.stream),
+             "z contract");
   }
   const FinGeo fg{sh.nbx[d], sh.nbq[d], 1.0 / (double)G.N};
   Launch L(e, K_FINAL, d);
@@ -725,10 +745,11 @@ void pass_back(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act
 }
 
 template <typename T>
-void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt, int c0) {
-  pass_front<T>(e, sh, tb, act, n);
+void iteration(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt, int c0,
+               int green) {
+  pass_front<T>(e, sh, tb, act, n, green);
   pass_x<T>(e, sh, tb, act, n, cnt, 0);
-  pass_back<T>(e, sh, tb, act, n, c0);
+  pass_back<T>(e, sh, tb, act, n, c0, green);
 }
 
 // the strain-based form (Algorithm 2): the strains are the iterate, the contraction
@@ -738,7 +759,7 @@ void iteration_strain(Engine& e, const Shape& sh, const ShapeTables& tb, const i
                       int c0) {
   pass_front_strain<T>(e, sh, tb, act, n);
   pass_x<T>(e, sh, tb, act, n, cnt, 0);
-  pass_back<T>(e, sh, tb, act, n, c0);
+  pass_back<T>(e, sh, tb, act, n, c0, GREEN_TETRA);
 }
 
 // the same iteration in the stencil form: 3-field transforms around the real-space
@@ -984,7 +1005,8 @@ std::vector<Prob*> Engine::tick() {
   std::vector<Seg> segs;
   auto put = [&](int cat, Prob* p) {
     for (auto& s : segs)
-      if (s.cat == cat && s.proto->tab.plans == p->tab.plans && (cat < 4 || s.proto->form == p->form)) {
+      if (s.cat == cat && s.proto->tab.plans == p->tab.plans &&
+          (cat < 4 || (s.proto->form == p->form && s.proto->green == p->green))) {
         s.ps.push_back(p);
         return;
       }
@@ -1107,10 +1129,10 @@ std::vector<Prob*> Engine::tick() {
     if (s.cat == 4) {
       if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, c0);
       else if (form == HZ_SCHEME_STRAIN) iteration_strain<double>(*this, sh, tb, act, n, s.cnt, c0);
-      else iteration<double>(*this, sh, tb, act, n, s.cnt, c0);
+      else iteration<double>(*this, sh, tb, act, n, s.cnt, c0, s.proto->green);
     } else {
       if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, c0);
-      else iteration<float>(*this, sh, tb, act, n, s.cnt, c0);
+      else iteration<float>(*this, sh, tb, act, n, s.cnt, c0, s.proto->green);
     }
     hip_check(hipEventRecord(evs[s.ev0 + i], stream), "hipEventRecord");
   };
@@ -1332,7 +1354,7 @@ void output_fields(Engine& e, Prob& p, double* eps_dev, double* sig_dev) {
             "status H2D");
   hip_check(hipMemcpyAsync(e.d_active, e.h_active, 4, hipMemcpyHostToDevice, e.stream), "active H2D");
   if (p.form == HZ_SCHEME_STRAIN) pass_front_strain<double>(e, *p.shape, p.tab, e.d_active, 1);
-  else pass_front<double>(e, *p.shape, p.tab, e.d_active, 1);
+  else pass_front<double>(e, *p.shape, p.tab, e.d_active, 1, p.green);
   int cnt[4]{};
   cnt[(p.base.iso ? KIND_ISO : 0) | (p.base.tau64 ? KIND_EIG : 0)] = 1;
   pass_x<double>(e, *p.shape, p.tab, e.d_active, 1, cnt, 1);

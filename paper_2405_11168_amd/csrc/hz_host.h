@@ -38,6 +38,12 @@ template <typename T>
 hipError_t launch_xr2c(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template <typename T>
 hipError_t launch_stencil(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
+// continuous-frequency comparison operator (hz_green.hip, FP64): z kernels over `sub`
+// columns of a z tile at a time
+hipError_t launch_zexp_cont(const Desc*, const int*, int, const ZGeo&, int, float, const Plan*, const void*,
+                            hipStream_t);
+hipError_t launch_zcon_cont(const Desc*, const int*, int, const ZGeo&, int, float, const Plan*, const void*,
+                            hipStream_t);
 hipError_t launch_finalize(const Desc*, const int*, int, const FinGeo&, hipStream_t);
 hipError_t launch_accumulate(const Desc*, const int*, int, long long, hipStream_t);
 hipError_t launch_zero(const Desc*, const int*, int, int, long long, hipStream_t);
@@ -76,6 +82,8 @@ struct Shape {
     return YGeo{geo.N2, TXy[d], nlines, off, from_state, PYy[d], PYy[d] == lds_pitch(geo.N2) ? 4 : 31};
   }
   int nbx[2]{}, nbq[2]{};                      // partial-sum blocks of the x and z passes
+  int subc = 0;        // continuous operator: columns per LDS round of an FP64 z tile (0: N3 too large)
+  float rsubc6 = 0.f;  // 1 / (6 subc)
   // stencil form (every accepted grid, see make_split_plans)
   bool stencil = false;
   int TY3[2]{};  // rows per block of the 3-field x transforms
@@ -189,6 +197,7 @@ struct Prob {
   ShapeTables tab{};
   int prec = HZ_FP64;
   int form = HZ_SCHEME_SPECTRAL;  // realisation of the iteration (same iterates either way)
+  int green = HZ_GREEN_TETRA;     // gradient discretisation (the comparison operators: spectral form)
   int loading = HZ_LOAD_STRAIN;
   double E[6]{};      // applied mean strain, or applied stress under HZ_LOAD_STRESS
   double Eb0[6]{};    // mean strain of iterate 0: E, or lambda0^-1:sigma^a

@@ -29,6 +29,10 @@ struct Geo {
   long long N;     // N1 * N2 * N3
 };
 
+// Gradient discretisation: the tetrahedral stencil, or one of the comparison
+// operators of the paper's experiments (same values as HZ_GREEN_* of the C ABI)
+enum { GREEN_TETRA = 0, GREEN_ROTATED = 1, GREEN_CONTINUOUS = 2 };
+
 // Material kind of a problem, which selects the instantiation of the kernels that
 // apply the constitutive law: every phase isotropic, and eigenstrains present.
 enum { KIND_ISO = 1, KIND_EIG = 2 };
@@ -74,7 +78,7 @@ struct Desc {
   int fmode;             // stop rule: 0 plain, 1 sweep (measure only), 2 correction round, 3 FP32 round 0
   int src;               // expansion source: 0 u[parity], 1 FP64 anchor u64
   int inner_max;         // iteration cap of FP32 rounds
-  int pad;
+  int green;             // GREEN_TETRA, or a comparison operator (spectral form only)
 };
 // The ping-pong slot of the current iterate is status[ST_K] & 1: every problem
 // counts its own measured iterates, so problems that started at different times

@@ -67,11 +67,16 @@ __global__ __launch_bounds__(kThreads) void k_zexp(const Desc* __restrict__ desc
   __syncthreads();
   HZ_GLB cpx<T>* out = glb(reinterpret_cast<cpx<T>*>(d.spec)) + plane;
   const cpx<double> t1 = tw1[h1];
+  const bool rot = d.green == GREEN_ROTATED;
   for (int e = threadIdx.x; e < TX * N3; e += kThreads) {
     const int l3 = fdiv(e, zg.rTX), col = e - l3 * TX;
     const int lm = l3 == 0 ? N3 - 1 : l3 - 1;
     cpx<double> a1[3], b1[3], a2[3], b2[3];
     affine_symbols(t1, tw2[h2_0 + col], a1, b1, a2, b2);
+    if (rot) {
+      rotated_mean(a1, a2);
+      rotated_mean(b1, b2);
+    }
     cpx<double> U[3], Um[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

@@ -55,6 +55,7 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
   const HZ_GLB cpx<T>* sp = glb(reinterpret_cast<const cpx<T>*>(d.spec)) + plane;
   const cpx<double> t1 = tw1[h1];
   const int ne = TX * N3;
+  const bool rot = !STENCIL && d.green == GREEN_ROTATED;  // the stencil form is tetrahedral
   if (STENCIL) {
     __syncthreads();  // twiddles
     const GblAcc<T> src{const_cast<HZ_GLB cpx<T>*>(sp) + 9 * zg.S, (int)zg.S, TX, 1, N2};
@@ -69,6 +70,10 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
     {
       cpx<double> a1[3], b1[3], a2[3], b2[3];
       affine_symbols(t1, tw2[h2_0 + col], a1, b1, a2, b2);
+      if (rot) {
+        rotated_mean(a1, a2);
+        rotated_mean(b1, b2);
+      }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         a1[c] = conjg(a1[c]); b1[c] = conjg(b1[c]); a2[c] = conjg(a2[c]); b2[c] = conjg(b2[c]);
@@ -173,6 +178,9 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
       }
       cpx<double> D1[3], D2[3];
       symbols(t1, t2v[i], t3v[i], D1, D2);
+      // M_jk = Re(conj(D1_j) D1_k + conj(D2_j) D2_k): with D~2 = -conj(D) times the phase
+      // (tetrahedral) and with D1 = D2 (rotated) alike it is 2 Re(conj(D1_j) D1_k)
+      if (rot) rotated_mean(D1, D2);
       // K_il = sum_jk C0_ijkl M_jk,  M_jk = 2 Re(conj(D_j) D_k)
       double Mjk[3][3];
 #pragma unroll
@@ -200,7 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
             K[a][l] = acc;
           }
       }
-      const bool sing = (h1 == 0 && h2 == 0 && h3 == 0) || (2 * h1 == zg.N1 && 2 * h2 == N2 && 2 * h3 == N3);
+      const int npi = (2 * h1 == zg.N1) + (2 * h2 == N2) + (2 * h3 == N3);
+      // Omega := 0 at q = 0 and where D vanishes: (pi,pi,pi) for the tetrahedral
+      // stencil, every q with two components at pi for the rotated one
+      const bool sing = (h1 == 0 && h2 == 0 && h3 == 0) || npi >= (rot ? 2 : 3);
       // Omega = K^-1 by the adjugate (K symmetric)
       const double a00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
       const double a01 = K[0][2] * K[2][1] - K[0][1] * K[2][2];
