@@ -31,6 +31,10 @@ Prints ONE JSON line:
   time_to_1e-6   FP32+refinement vs plain FP64 device time to an FP64-verified
                  residual of 1e-6 on the 256^3 Voronoi polycrystal (6 loads); the speedup
                  only when every load of both solves converged
+  green_operators  the comparison Green operators of Sec. 3.2 / Appendix B (rotated,
+                 continuous-frequency) beside the tetrahedral scheme: the 64^3 cubic void
+                 under 300 MPa (iterates to 1e-4/1e-6/1e-10, artefact measures of the
+                 stress field) and the FP64 iteration rate of each on the headline workload
   serving        a seeded stream of solve requests (grid sizes 32..192^3, Boolean
                  spheres or cubic polycrystals, contrast log-uniform 1e1..1e6, one
                  load each, FP32+refine to 1e-6) through the solve server: closed-loop
@@ -235,6 +239,112 @@ def full_size_leg(hz, np, torch, name, p, g, loads, K1=4, K2=24):
                     "kernels": {k: v for k, v in kernel_rates(prof, S, N, nl).items()
                                 if k.endswith("f64" if key == "fp64" else "f32")}}
     return out
+
+
+def compare_leg(syn, hz, np, torch, K1=4, K2=24, parts=("void", "rates")):
+    """The comparison Green operators of Sec. 3.2 and Appendix B beside the tetrahedral
+    scheme (FP64; the comparison operators run in the spectral form).
+
+    (1) The cubic void of Sec. 3.2 at the paper's size: a 31^3 void in a 64^3 cell
+    (mu = 132.30 GPa, nu = 0.26), hydrostatic pressure 300 MPa as an applied stress,
+    lambda0 = 0.8 lambda_m, run to eps < 1e-10 (cap 4000 iterates, traced): iterates to
+    1e-4, 1e-6 and 1e-10, device seconds, and two measures of the artefacts the paper
+    shows in its stress maps, taken on the stress field of the reported iterate:
+    'checkerboard_frac', the share of the stress field's spectral energy (q != 0) on
+    the lines where two components of q equal pi (the rotated scheme's zero set), and
+    'line_osc_MPa', the largest second difference of sigma_11 along the (100) line
+    through the void centre, over matrix voxels at least two voxels from a void face.
+    (2) The iteration rate of each operator on the headline workload (128^3 Boolean
+    spheres, contrast 1e3, 6 loads), from two fixed-length runs, with per-kernel rates."""
+    out = {}
+    ops = (("tetra_stencil", hz.HZ_GREEN_TETRA, hz.HZ_SCHEME_STENCIL),
+           ("tetra_spectral", hz.HZ_GREEN_TETRA, hz.HZ_SCHEME_SPECTRAL),
+           ("rotated", hz.HZ_GREEN_ROTATED, hz.HZ_SCHEME_AUTO),
+           ("continuous", hz.HZ_GREEN_CONTINUOUS, hz.HZ_SCHEME_AUTO))
+    if "void" in parts:
+        out["cubic_void"] = cubic_void_compare(syn, hz, np, ops)
+    if "rates" in parts:
+        out["iteration_rate"] = compare_rates(syn, hz, np, torch, ops, K1, K2)
+    return out
+
+
+def cubic_void_compare(syn, hz, np, ops):
+    N = 64
+    ph = np.zeros((N, N, N), dtype=np.uint16)
+    ph[16:47, 16:47, 16:47] = 1
+    mu, nu = 132.30e3, 0.26
+    Cm = syn.isotropic_voigt(2.0 * mu * (1.0 + nu), nu)
+    C = np.stack([Cm, np.zeros((6, 6))])
+    sa = np.array([[-300.0, -300.0, -300.0, 0.0, 0.0, 0.0]])
+    g = hz.Grid(N, N, N)
+    g.set_material(C, ph)
+    h = np.arange(N)
+    lines = (((2 * h == N)[:, None, None].astype(int) + (2 * h == N)[None, :, None]
+              + (2 * h == N)[None, None, :]) >= 2)
+    lines[0, 0, 0] = False
+    x = np.arange(N)
+    matrix = (x < 16 - 2) | (x > 46 + 2)
+    void = {"workload": "cubic void 31^3 in 64^3, P = 300 MPa, lambda0 = 0.8 lambda_m", "tol": 1e-10, "cap": 4000}
+    for name, green, scheme in ops:
+        r = g.solve(sa, C0=0.8 * Cm, tol=1e-10, max_iters=4000, loading=hz.HZ_LOAD_STRESS, fields=True,
+                    trace=True, scheme=scheme, green=green)
+        tr = r.trace_residual[0]
+        tr = tr[np.isfinite(tr)]
+
+        def first(t):
+            k = np.nonzero(tr < t)[0]
+            return int(k[0]) if k.size else None
+
+        sig = r.sigma[0]
+        spec = np.fft.fftn(sig, axes=(1, 2, 3))
+        e = np.sum(np.abs(spec) ** 2, axis=0)
+        e[0, 0, 0] = 0.0
+        s11 = sig[0, 31, 31, :]
+        d2 = np.abs(np.roll(s11, -1) - 2 * s11 + np.roll(s11, 1))
+        void[name] = {"status": int(r.status[0]), "iters": int(r.iters[0]), "residual": float(r.residual[0]),
+                      "iters_to_1e-4": first(1e-4), "iters_to_1e-6": first(1e-6), "iters_to_1e-10": first(1e-10),
+                      "seconds": round(float(r.seconds[0]), 4),
+                      "checkerboard_frac": float(e[lines].sum() / e.sum()),
+                      "line_osc_MPa": round(float(d2[matrix].max()), 4),
+                      "mean_sigma": [round(float(v), 6) for v in r.mean_sigma[0][:3]]}
+        log(f"bench: compare cubic void {name}: {void[name]}")
+    return void
+
+
+def compare_rates(syn, hz, np, torch, ops, K1, K2):
+    p = syn.boolean128()
+    g = hz.Grid(*p.shape)
+    g.set_material(p.C, p.phase)
+    g.bind(hz.HZ_FP64, 6)
+    N1, N2, N3 = p.shape
+    Nv, S = N1 * N2 * N3, (N1 // 2 + 1) * N2 * N3
+    rates = {"workload": "boolean128_c1e3_6loads", "passes_timed": K2 - K1}
+    for name, green, scheme in ops:
+        def run(K):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = g.solve(p.loads, C0=p.C0, fixed_iters=K, check_every=1 << 20, scheme=scheme, green=green)
+            torch.cuda.synchronize()
+            assert np.all(r.iters == K), r.iters
+            return time.perf_counter() - t0
+
+        run(2)
+        t1, t2 = run(K1), run(K2)
+        g.profile(True)
+        run(K2)
+        torch.cuda.synchronize()
+        g.profile(False)
+        prof = g.profile_read()
+        per_iter = (t2 - t1) / (K2 - K1)
+        form = "stencil" if scheme == hz.HZ_SCHEME_STENCIL else "spectral"
+        bpv = iteration_bytes(form, S, Nv, 16) / Nv
+        vips = Nv * 6 / per_iter
+        rates[name] = {"ms_per_iteration": round(per_iter * 1e3, 4), "voxel_iters_per_s": vips,
+                       "bytes_per_voxel_iteration": round(bpv, 1),
+                       "iteration_roofline_frac": round(vips * bpv / (HBM_PEAK_GBS * 1e9), 4),
+                       "kernels": kernel_rates(prof, S, Nv, 6)}
+        log(f"bench: compare rate {name}: {per_iter * 1e3:.3f} ms per 6-load iteration, {vips / 1e9:.2f} G")
+    return rates
 
 
 def bounds_margins(np, Ce, C, phase):
@@ -573,8 +683,8 @@ def headline(a, hz, np, torch, p, g, copy_gbps):
     }
 
 
-LEGS = ("iter", "ceff", "full", "ttt", "serve", "cpu", "sweep")
-DEFAULT_LEGS = ("iter", "ceff", "full", "ttt", "serve", "cpu")
+LEGS = ("iter", "ceff", "full", "ttt", "serve", "cpu", "sweep", "compare")
+DEFAULT_LEGS = ("iter", "ceff", "full", "ttt", "compare", "serve", "cpu")
 FULL = ("voronoi256", "spheres192x192x320")
 
 
@@ -602,6 +712,8 @@ def main():
     ap.add_argument("--sweep-grids", default="256x256x256,192x192x320", help="grids of the contrast sweep")
     ap.add_argument("--sweep-contrasts", default="0,1e-4,1e-2,10,1e2,1e3,1e4,1e6,1e8",
                     help="inclusion-to-matrix stiffness ratios of the contrast sweep")
+    ap.add_argument("--compare-parts", default="void,rates",
+                    help="parts of the compare leg: void (cubic void of Sec. 3.2), rates (iteration rates)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
     a = ap.parse_args()
@@ -688,6 +800,9 @@ def main():
     if "sweep" in legs:
         grids = [tuple(int(v) for v in t.split("x")) for t in a.sweep_grids.split(",") if t]
         out["contrast_sweep"] = sweep_leg(syn, hz, np, torch, grids, [float(c) for c in a.sweep_contrasts.split(",")])
+    if "compare" in legs:
+        log("bench: comparison Green operators (cubic void of Sec. 3.2, iteration rates)")
+        out["green_operators"] = compare_leg(syn, hz, np, torch, parts=tuple(a.compare_parts.split(",")))
     if "serve" in legs:
         log(f"bench: serving leg ({a.serve_n} requests)")
         out["serving"] = serving_leg(syn, hz, np, torch, a.serve_n, a.serve_max_iters, streams=a.serve_streams,
