@@ -122,7 +122,7 @@ def host_cpu():
     return model, avail
 
 
-def cpu_baseline(problem, max_seconds=15.0):
+def cpu_baseline(problem, max_seconds=20.0):
     """The oracle (FP64 numpy/scipy, Algorithm 1) on a bounded sample: one load,
     a few iterations of the same 128^3 workload, timed on the host."""
     from oracle import tetra

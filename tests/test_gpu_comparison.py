@@ -149,3 +149,25 @@ def test_rejected_combinations():
             g.solve(E, C0=p.C0, green=hz.HZ_GREEN_ROTATED, **kw)
     with pytest.raises(hz.HzError):
         g.solve(E, C0=p.C0, green=7)
+
+
+@pytest.mark.parametrize("op", list(OPS))
+def test_full_size_boolean128_first_iterates(op):
+    """The 128^3 Boolean-sphere workload (contrast 1e3, 6 loads) in the launch
+    configuration the compare leg of the benchmark times: iterates 0..2 of two loads
+    against the oracle, residual and <sigma> at every iterate and u_2 element by element."""
+    p = syn.boolean128()
+    g = hz.Grid(*p.shape)
+    g.set_material(p.C, p.phase)
+    K = 2
+    _say(f"comparison operator {op}, boolean128, 6 loads")
+    r = g.solve(p.loads, precision=hz.HZ_FP64, C0=p.C0, fixed_iters=K, trace=True, green=OPS[op])
+    for J in (0, 5):
+        ref = comparison.basic_scheme(p.phase, p.C, p.C0, p.loads[J], op, fixed_iters=K)
+        eh = np.max(np.abs(r.trace_residual[J, : K + 1] - ref.history) / ref.history)
+        em = np.abs(r.trace_mean[J, : K + 1] - ref.mean_history).max() / np.abs(ref.mean_history).max()
+        u = g.displacement(J)
+        uo = oracle_u_lib(op, ref.u_hat, p.shape)
+        eu = np.abs(u - uo).max() / np.abs(uo).max()
+        _say(f"  {op} boolean128 load {J}: residual hist {eh:.2e} <sigma> {em:.2e} u {eu:.2e}")
+        assert eh < 1e-10 and em < 1e-12 and eu < 1e-11
