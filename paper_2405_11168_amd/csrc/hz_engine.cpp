@@ -190,8 +190,8 @@ void Shape::init(int n1, int n2, int n3) {
     const int rowcap = 256 / csz;               // TX giving 256-byte rows
     // z kernels: 3 comps x TX columns x N3 in LDS (+ N3 twiddles), TX | N2
     int tx = std::min(rowcap, G.N2);
-    while (tx > 1 && (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes || G.N2 % tx)) --tx;
-    if (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytes) fail(HZ_EINVAL, "N3 too large");
+    while (tx > 1 && (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytesZ || G.N2 % tx)) --tx;
+    if (3 * tx * G.N3 > tile || (3 * tx * G.N3 + G.N3) * csz > kLdsBytesZ) fail(HZ_EINVAL, "N3 too large");
     TXz[d] = tx;
     if (d) {
       // continuous operator: 6 lines per column, the largest divisor of tx that fits

@@ -65,6 +65,10 @@ constexpr int kTraceCap = 4097;        // iterates recorded per load (eps_k, <si
 constexpr int kMaxIters = 1000000;     // cap on max_iters
 constexpr int kMaxLanes = 8;           // streams a server may spread iterate groups over
 constexpr int kLdsBytes = 65536 - 512;  // LDS budget of one work-group
+// LDS budget of a z-kernel work-group (3 components x TX columns x N3 and the twiddles):
+// above 64 KB where that keeps a tile's rows at 4 FP64 columns (64-byte segments) for
+// N3 up to 340, instead of 3 (48-byte segments, partly wasted HBM transactions)
+constexpr int kLdsBytesZ = 68 * 1024;
 
 float recip(int d);
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }

@@ -29,6 +29,15 @@ struct Geo {
   long long N;     // N1 * N2 * N3
 };
 
+// Dynamic LDS of a work-group beyond 64 KB (gfx950 has 160 KB per CU; the z kernels
+// of some grids take up to kLdsBytesZ) needs the kernel's limit raised before the launch.
+template <class F>
+inline hipError_t allow_lds(F* kernel, size_t bytes) {
+  if (bytes <= 65536 - 512) return hipSuccess;  // room for the kernels' static LDS
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
 // Gradient discretisation: the tetrahedral stencil, or one of the comparison
 // operators of the paper's experiments (same values as HZ_GREEN_* of the C ABI)
 enum { GREEN_TETRA = 0, GREEN_ROTATED = 1, GREEN_CONTINUOUS = 2 };

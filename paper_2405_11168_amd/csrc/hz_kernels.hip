@@ -456,6 +456,8 @@ hipError_t launch_zexp(const Desc* descs, const int* active, int nact, const ZGe
                        const void* tw3T, const void* tw1, const void* tw2, hipStream_t s) {
   const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
   dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
+  const hipError_t e = allow_lds(k_zexp<T>, shm);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_zexp<T>, grid, dim3(kThreads), shm, s, descs, active, zg, *plan3, (const cpx<T>*)tw3T,
                      (const cpx<double>*)tw1, (const cpx<double>*)tw2);
   return hipGetLastError();
@@ -511,6 +513,8 @@ hipError_t launch_zstrain(const Desc* descs, const int* active, int nact, const 
                           const void* tw3T, const void* tw1, const void* tw2, const void* tw3, hipStream_t s) {
   const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
   dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
+  const hipError_t e = allow_lds(k_zstrain<T>, shm);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_zstrain<T>, grid, dim3(kThreads), shm, s, descs, active, zg, *plan3, (const cpx<T>*)tw3T,
                      (const cpx<double>*)tw1, (const cpx<double>*)tw2, (const cpx<double>*)tw3);
   return hipGetLastError();

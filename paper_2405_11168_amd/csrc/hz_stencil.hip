@@ -562,6 +562,8 @@ hipError_t launch_zconv3(void* u, bool inverse, const ZGeo& zg, const Plan* plan
   const dim3 grid((unsigned)(zg.H1 * zg.tiles));
   cpx<double>* p = reinterpret_cast<cpx<double>*>(u);
   const cpx<double>* tw = (const cpx<double>*)tw3;
+  const hipError_t e = inverse ? allow_lds(k_zconv3<true>, shm) : allow_lds(k_zconv3<false>, shm);
+  if (e != hipSuccess) return e;
   if (inverse) hipLaunchKernelGGL(k_zconv3<true>, grid, dim3(kThreads), shm, s, p, zg, *plan3, tw, 1.0);
   else hipLaunchKernelGGL(k_zconv3<false>, grid, dim3(kThreads), shm, s, p, zg, *plan3, tw, 1.0 / zg.N3);
   return hipGetLastError();

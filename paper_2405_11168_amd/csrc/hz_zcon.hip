@@ -443,27 +443,32 @@ __global__ __launch_bounds__(kThreads) void k_zero(const Desc* __restrict__ desc
 // launch wrappers
 // ----------------------------------------------------------------------------
 template <typename T, bool STENCIL, bool C0ISO>
-void launch_zcon1(const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
-                  const void* tw3T, const void* tw1, const void* tw2, const void* tw3, hipStream_t s) {
+hipError_t launch_zcon1(const Desc* descs, const int* active, int nact, const ZGeo& zg, const Plan* plan3,
+                        const void* tw3T, const void* tw1, const void* tw2, const void* tw3, hipStream_t s) {
   const size_t shm = ((size_t)3 * zg.TX * zg.N3 + zg.N3) * sizeof(cpx<T>);
   dim3 grid((unsigned)(zg.H1 * zg.tiles), nact);
+  const hipError_t e = allow_lds(k_zcon<T, STENCIL, C0ISO>, shm);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_zcon<T, STENCIL, C0ISO>), grid, dim3(kThreads), shm, s, descs, active, zg, *plan3,
                      (const cpx<T>*)tw3T, (const cpx<double>*)tw1, (const cpx<double>*)tw2, (const cpx<double>*)tw3);
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_zcon(const Desc* descs, const int* active, int nact, bool stencil, int c0, const ZGeo& zg,
                        const Plan* plan3, const void* tw3T, const void* tw1, const void* tw2, const void* tw3,
                        hipStream_t s) {
+  hipError_t e = hipSuccess;
   if (c0 & 1) {
-    if (stencil) launch_zcon1<T, true, true>(descs, active, nact, zg, plan3, tw3T, tw1, tw2, tw3, s);
-    else launch_zcon1<T, false, true>(descs, active, nact, zg, plan3, tw3T, tw1, tw2, tw3, s);
+    e = stencil ? launch_zcon1<T, true, true>(descs, active, nact, zg, plan3, tw3T, tw1, tw2, tw3, s)
+                : launch_zcon1<T, false, true>(descs, active, nact, zg, plan3, tw3T, tw1, tw2, tw3, s);
+    if (e != hipSuccess) return e;
   }
   if (c0 & 2) {
-    if (stencil) launch_zcon1<T, true, false>(descs, active, nact, zg, plan3, tw3T, tw1, tw2, tw3, s);
-    else launch_zcon1<T, false, false>(descs, active, nact, zg, plan3, tw3T, tw1, tw2, tw3, s);
+    e = stencil ? launch_zcon1<T, true, false>(descs, active, nact, zg, plan3, tw3T, tw1, tw2, tw3, s)
+                : launch_zcon1<T, false, false>(descs, active, nact, zg, plan3, tw3T, tw1, tw2, tw3, s);
   }
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_finalize(const Desc* descs, const int* active, int nact, const FinGeo& fg,

@@ -44,7 +44,8 @@ def test_size_checks():
 
 def test_size_limits_and_both_schemes_on_every_accepted_grid():
     """Each axis up to the largest 7-smooth even size whose FP64 transform tile fits the
-    64 KB of LDS the transforms use (N1, N3 <= 1008, N2 <= 2016), a load's 12 spectra under
+    LDS the transforms use (64 KB for x and y: N1 <= 1008, N2 <= 2016; 68 KB for z:
+    N3 <= 1080), a load's 12 spectra under
     2^31 complex elements (700^3 accepted, 720^3 refused); on every accepted grid both
     forms are available, the stencil form's x transforms splitting on an odd radix, or in
     one pass, where N1/2 has no factor 2."""
@@ -52,7 +53,7 @@ def test_size_limits_and_both_schemes_on_every_accepted_grid():
     h = ctypes.c_void_p()
     for shape, code in [((1008, 8, 8), hz.HZ_OK), ((1024, 8, 8), _abi.HZ_EINVAL),
                         ((8, 2016, 8), hz.HZ_OK), ((8, 2048, 8), _abi.HZ_EINVAL),
-                        ((8, 8, 1008), hz.HZ_OK), ((8, 8, 1024), _abi.HZ_EINVAL),
+                        ((8, 8, 1080), hz.HZ_OK), ((8, 8, 1120), _abi.HZ_EINVAL),
                         ((700, 700, 700), hz.HZ_OK), ((720, 720, 720), _abi.HZ_EINVAL)]:
         assert lib.hz_create_grid(*shape, ctypes.byref(h)) == code, shape
         if code == hz.HZ_OK:

@@ -114,6 +114,10 @@ def check_pair(shape, g, r, ref, K, fields=True):
     ((126, 8, 6), 2, 20, "iso", False, 3),
     ((10, 6, 8), 2, 21, "iso", True, 5),
     ((126, 96, 80), 3, 22, "aniso", False, 2),   # odd split radix over many tiles (63 = 3, 7, 3)
+    # z tiles whose LDS exceeds 64 KB: 4 FP64 columns of N3 = 320 (66.5 KB), and the longest
+    # z lines, N3 = 1080 (one column, 67.5 KB)
+    ((8, 8, 320), 2, 24, "aniso", False, 2),
+    ((6, 4, 1080), 2, 25, "iso", True, 2),
     ((8, 2016, 8), 2, 23, "iso", False, 2),      # longest y lines: FP64 lines unpadded in LDS
 ])
 @pytest.mark.parametrize("scheme", SCHEMES, ids=["spectral", "stencil"])
