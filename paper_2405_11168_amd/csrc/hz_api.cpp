@@ -120,6 +120,7 @@ void setup_prob(Prob& p, int slot, const Shape* sh, const ShapeTables& tab, cons
   d.tau64 = mt.tau64;
   d.tau32 = mt.tau32;
   d.green = o.green;
+  d.n_phases = m.n_phases;
   d.loading = o.loading;
   if (o.loading == HZ_LOAD_STRESS) {
     auto frob = [](const double* t) {

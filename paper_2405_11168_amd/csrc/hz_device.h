@@ -205,9 +205,11 @@ __device__ __forceinline__ void constitutive(const HZ_GLB T* __restrict__ Cp, co
 // the same law for the two tetrahedra of one voxel (one phase): the stiffness entries
 // are loaded once for both and each is used as it arrives (C_ab enters sigma_a and, off
 // the diagonal, sigma_b), so only a few of them are live at a time
-template <bool EIG, typename T>
-__device__ __forceinline__ void constitutive_pair(const HZ_GLB T* __restrict__ Cp, const Mean<T>& M, int ph,
-                                                  const T (&de0)[6], const T (&de1)[6], T (&s0)[6], T (&s1)[6]) {
+// ld(i) returns the i-th complex pair of the phase's 24-slot row (from HBM or from a
+// copy of the table in LDS)
+template <bool EIG, typename T, class LD>
+__device__ __forceinline__ void constitutive_pair_ld(LD ld, const Mean<T>& M, int ph, const T (&de0)[6],
+                                                     const T (&de1)[6], T (&s0)[6], T (&s1)[6]) {
   T g0[6], g1[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -225,7 +227,7 @@ __device__ __forceinline__ void constitutive_pair(const HZ_GLB T* __restrict__ C
   // k = 6..10, a = 2 k = 11..14, a = 3 k = 15..17, a = 4 k = 18..19, a = 5 k = 20
 #pragma unroll
   for (int k2 = 0; k2 < 21; k2 += 2) {
-    const cpx<T> v = gld(reinterpret_cast<const HZ_GLB cpx<T>*>(Cp) + k2 / 2);
+    const cpx<T> v = ld(k2 / 2);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int k = k2 + h;
@@ -243,6 +245,12 @@ __device__ __forceinline__ void constitutive_pair(const HZ_GLB T* __restrict__ C
   }
   eigenstress<EIG>(M, ph, s0);
   eigenstress<EIG>(M, ph, s1);
+}
+template <bool EIG, typename T>
+__device__ __forceinline__ void constitutive_pair(const HZ_GLB T* __restrict__ Cp, const Mean<T>& M, int ph,
+                                                  const T (&de0)[6], const T (&de1)[6], T (&s0)[6], T (&s1)[6]) {
+  const HZ_GLB cpx<T>* row = reinterpret_cast<const HZ_GLB cpx<T>*>(Cp);
+  constitutive_pair_ld<EIG, T>([&](int i) { return gld(row + i); }, M, ph, de0, de1, s0, s1);
 }
 
 // isotropic phase: sigma = lambda tr(eps) I + 2 mu eps - lambda:eps0

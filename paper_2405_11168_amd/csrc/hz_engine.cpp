@@ -768,6 +768,7 @@ void iteration_strain(Engine& e, const Shape& sh, const ShapeTables& tb, const i
 // transform of the state and the contraction updates the state in that domain.
 template <typename T>
 void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const int* act, int n, const int* cnt,
+                       const int* maxph,
                        int c0) {
   const int d = sizeof(T) == 8;
   const Geo& G = sh.geo;
@@ -790,7 +791,7 @@ void iteration_stencil(Engine& e, const Shape& sh, const ShapeTables& tb, const 
   {
     Launch L(e, K_STEN, d);
     for (int k = 0, off = 0; k < 4; off += cnt[k++])
-      if (cnt[k] > 0) L.done(launch_stencil<T>(e.d_desc, act + off, cnt[k], k, sh.sg, e.stream), "stencil");
+      if (cnt[k] > 0) L.done(launch_stencil<T>(e.d_desc, act + off, cnt[k], k, maxph[k], sh.sg, e.stream), "stencil");
   }
   {
     const Plan& pf = sh.plans[7];
@@ -1001,6 +1002,7 @@ std::vector<Prob*> Engine::tick() {
     std::vector<Prob*> ps;
     int off = 0, K = 0, ev0 = 0;
     int cnt[4]{};  // problems of each material kind, in kind order
+    int maxph[4]{};  // most phases among the problems of each kind (stiffness tables in LDS)
   };
   std::vector<Seg> segs;
   auto put = [&](int cat, Prob* p) {
@@ -1044,7 +1046,10 @@ std::vector<Prob*> Engine::tick() {
   for (auto& s : segs)
     if (s.cat >= 4) {
       std::stable_sort(s.ps.begin(), s.ps.end(), [](const Prob* a, const Prob* b) { return kind_of(a) < kind_of(b); });
-      for (const Prob* p : s.ps) s.cnt[kind_of(p)]++;
+      for (const Prob* p : s.ps) {
+        s.cnt[kind_of(p)]++;
+        s.maxph[kind_of(p)] = std::max(s.maxph[kind_of(p)], p->base.n_phases);
+      }
     }
   int cur = 0;
   for (auto& s : segs) {
@@ -1127,11 +1132,11 @@ std::vector<Prob*> Engine::tick() {
     const Shape& sh = *s.proto->shape;
     const ShapeTables& tb = s.proto->tab;
     if (s.cat == 4) {
-      if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, c0);
+      if (form == HZ_SCHEME_STENCIL) iteration_stencil<double>(*this, sh, tb, act, n, s.cnt, s.maxph, c0);
       else if (form == HZ_SCHEME_STRAIN) iteration_strain<double>(*this, sh, tb, act, n, s.cnt, c0);
       else iteration<double>(*this, sh, tb, act, n, s.cnt, c0, s.proto->green);
     } else {
-      if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, c0);
+      if (form == HZ_SCHEME_STENCIL) iteration_stencil<float>(*this, sh, tb, act, n, s.cnt, s.maxph, c0);
       else iteration<float>(*this, sh, tb, act, n, s.cnt, c0, s.proto->green);
     }
     hip_check(hipEventRecord(evs[s.ev0 + i], stream), "hipEventRecord");

@@ -37,7 +37,7 @@ hipError_t launch_xc2r(const Desc*, const int*, int, const XGeo&, const Plan*, i
 template <typename T>
 hipError_t launch_xr2c(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template <typename T>
-hipError_t launch_stencil(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
+hipError_t launch_stencil(const Desc*, const int*, int, int, int, const SGeo&, hipStream_t);
 // continuous-frequency comparison operator (hz_green.hip, FP64): z kernels over `sub`
 // columns of a z tile at a time
 hipError_t launch_zexp_cont(const Desc*, const int*, int, const ZGeo&, int, float, const Plan*, const void*,

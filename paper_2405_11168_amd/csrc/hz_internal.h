@@ -76,7 +76,7 @@ struct Desc {
   double S0[36];         // stress loading: lambda0^-1 acting on tensor comps, row-major
   double sref;           // stress loading: fixed stress scale of the stop rule
   int loading;           // 0 applied mean strain, 1 applied stress (Sec. 2.5)
-  int pad0;
+  int n_phases;          // rows of the stiffness tables
   double C0[81];         // reference medium, full 3x3x3x3 tensor
   double tol;
   int max_iters;

@@ -310,8 +310,12 @@ constexpr int stencil_waves() { return sizeof(T) == 8 ? 3 : 4; }
 // depend on their order, so every run gives the same bits.
 template <typename T, bool ISO, bool EIG>
 __global__ __launch_bounds__(kThreads, stencil_waves<T>()) void k_stencil(const Desc* __restrict__ descs, const int* __restrict__ active,
-                                                      SGeo sg) {
+                                                      SGeo sg, int tab_bytes) {
   static_assert(kStX == 64 && kStY * 64 == kThreads, "one wave per corner row");
+  // anisotropic phases: the stiffness table in LDS when it fits tab_bytes, so the per-voxel
+  // rows are LDS gathers instead of HBM/L2 gathers issued at the point of use
+  extern __shared__ __align__(16) unsigned char smem_dyn[];
+  cpx<T>* ctab = reinterpret_cast<cpx<T>*>(smem_dyn);
   __shared__ T lh[kStY][kStZ + 2][6];     // u at column x0 - 1: row below (0..2), own row (3..5)
   __shared__ T hr[kStY][kStZ + 1][4][3];  // halo voxel column: contribution to column x0+wx-1, [dy*2 + dz]
   __shared__ T xb[2][kStY][3][64];        // row y + 1 terms of corner row y
@@ -332,6 +336,10 @@ __global__ __launch_bounds__(kThreads, stencil_waves<T>()) void k_stencil(const 
   const HZ_GLB cpx<T>* Clm = reinterpret_cast<const HZ_GLB cpx<T>*>(C);
   const Mean<T> Mn = mean_state<T>(d);
   const HZ_GLB uint16_t* ph = glb(d.phase);
+  const bool tab = !ISO && d.n_phases * 24 * (int)sizeof(T) <= tab_bytes;
+  if (tab) {
+    for (int i = threadIdx.x; i < d.n_phases * 12; i += kThreads) ctab[i] = gld(Clm + i);
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool wact = w < wy, xact = lane < wx;
   const int y = y0 + (wact ? w : 0);  // waves past the tile's last row shadow its first (results unused)
@@ -477,7 +485,12 @@ __global__ __launch_bounds__(kThreads, stencil_waves<T>()) void k_stencil(const 
       if constexpr (ISO) constitutive_iso<EIG, T>(lmc.x, lmc.y, Mn, phc, e, s2);
       else {
         const T e1s[6] = {s1[0], s1[1], s1[2], s1[3], s1[4], s1[5]};
-        constitutive_pair<EIG, T>(C + phc * 24, Mn, phc, e1s, e, s1, s2);
+        if (tab) {
+          const cpx<T>* row = ctab + phc * 12;
+          constitutive_pair_ld<EIG, T>([&](int k) { return row[k]; }, Mn, phc, e1s, e, s1, s2);
+        } else {
+          constitutive_pair<EIG, T>(C + phc * 24, Mn, phc, e1s, e, s1, s2);
+        }
       }
     }
     // issue order: moduli of plane p + 1 (needed first), phase ids of plane p + 2,
@@ -609,14 +622,33 @@ hipError_t launch_xr2c(const Desc* descs, const int* active, int nact, const XGe
   return hipGetLastError();
 }
 
+// Largest stiffness table the anisotropic variants copy to LDS (24 slots per phase):
+// 200 rotated grains.  Beside the kernel's static buffers (about 32 KB FP64, 16 KB FP32)
+// a table that size leaves FP32 at its 4 work-groups per CU and takes FP64 from 3 to 2,
+// which still measured faster at 200 grains than gathering the rows from L2 at 3.
 template <typename T>
-hipError_t launch_stencil(const Desc* descs, const int* active, int nact, int kind, const SGeo& sg, hipStream_t s) {
+constexpr int stencil_tab_cap() { return sizeof(T) == 8 ? 38400 : 24 * 1024; }
+
+// max_phases: the most phases among the launch's problems; the launch reserves LDS for
+// that table if it fits the cap, else none (each block checks its own problem)
+template <typename T>
+hipError_t launch_stencil(const Desc* descs, const int* active, int nact, int kind, int max_phases, const SGeo& sg,
+                          hipStream_t s) {
   dim3 grid((unsigned)(sg.tx * sg.ty * sg.tz), nact);
+  const int need = max_phases * 24 * (int)sizeof(T);
+  const int tb = (kind & KIND_ISO) || need > stencil_tab_cap<T>() ? 0 : need;
+  if (kind == 0) {
+    const hipError_t e = allow_lds(k_stencil<T, false, false>, tb + 32 * 1024);
+    if (e != hipSuccess) return e;
+  } else if (kind == KIND_EIG) {
+    const hipError_t e = allow_lds(k_stencil<T, false, true>, tb + 32 * 1024);
+    if (e != hipSuccess) return e;
+  }
   switch (kind) {
-    case KIND_ISO: hipLaunchKernelGGL((k_stencil<T, true, false>), grid, dim3(kThreads), 0, s, descs, active, sg); break;
-    case KIND_ISO | KIND_EIG: hipLaunchKernelGGL((k_stencil<T, true, true>), grid, dim3(kThreads), 0, s, descs, active, sg); break;
-    case 0: hipLaunchKernelGGL((k_stencil<T, false, false>), grid, dim3(kThreads), 0, s, descs, active, sg); break;
-    default: hipLaunchKernelGGL((k_stencil<T, false, true>), grid, dim3(kThreads), 0, s, descs, active, sg); break;
+    case KIND_ISO: hipLaunchKernelGGL((k_stencil<T, true, false>), grid, dim3(kThreads), 0, s, descs, active, sg, 0); break;
+    case KIND_ISO | KIND_EIG: hipLaunchKernelGGL((k_stencil<T, true, true>), grid, dim3(kThreads), 0, s, descs, active, sg, 0); break;
+    case 0: hipLaunchKernelGGL((k_stencil<T, false, false>), grid, dim3(kThreads), tb, s, descs, active, sg, tb); break;
+    default: hipLaunchKernelGGL((k_stencil<T, false, true>), grid, dim3(kThreads), tb, s, descs, active, sg, tb); break;
   }
   return hipGetLastError();
 }
@@ -625,7 +657,7 @@ template hipError_t launch_xc2r<double>(const Desc*, const int*, int, const XGeo
 template hipError_t launch_xc2r<float>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template hipError_t launch_xr2c<double>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
 template hipError_t launch_xr2c<float>(const Desc*, const int*, int, const XGeo&, const Plan*, int, const void*, hipStream_t);
-template hipError_t launch_stencil<double>(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
-template hipError_t launch_stencil<float>(const Desc*, const int*, int, int, const SGeo&, hipStream_t);
+template hipError_t launch_stencil<double>(const Desc*, const int*, int, int, int, const SGeo&, hipStream_t);
+template hipError_t launch_stencil<float>(const Desc*, const int*, int, int, int, const SGeo&, hipStream_t);
 
 }  // namespace hz
