@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 namespace hz {
 
 constexpr int kThreads = 256;   // work-group size of every kernel (4 wave64)
@@ -29,13 +33,28 @@ struct Geo {
   long long N;     // N1 * N2 * N3
 };
 
-// Dynamic LDS of a work-group beyond 64 KB (gfx950 has 160 KB per CU; the z kernels
-// of some grids take up to kLdsBytesZ) needs the kernel's limit raised before the launch.
+// Dynamic LDS of a work-group beyond 64 KB (gfx950 has 160 KB per CU; the z kernels of
+// some grids and the stencil kernel with a stiffness table take more) needs the kernel's
+// limit raised before the launch: once per kernel and device, to 96 KB, so launches
+// (also under stream capture) make no further runtime call.
+constexpr int kLdsDynMax = 96 * 1024;
+inline hipError_t allow_lds_once(const void* kernel) {
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count({kernel, dev})) return hipSuccess;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsDynMax);
+  if (e == hipSuccess) done.insert({kernel, dev});
+  return e;
+}
 template <class F>
 inline hipError_t allow_lds(F* kernel, size_t bytes) {
   if (bytes <= 65536 - 512) return hipSuccess;  // room for the kernels' static LDS
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+  if (bytes > (size_t)kLdsDynMax) return hipErrorInvalidValue;
+  return allow_lds_once(reinterpret_cast<const void*>(kernel));
 }
 
 // Gradient discretisation: the tetrahedral stencil, or one of the comparison
