@@ -303,6 +303,19 @@ def isolated_sphere(contrast: float, n: int = 48, radius_frac: float = 0.4, nu: 
                    {"contrast": contrast, "vf": float(ph.mean())})
 
 
+def hard_sphere(n: int = 128, radius: float = 40.0) -> Problem:
+    """The hard inclusion of Sec. 3.3: one glass sphere (E = 72 GPa, nu = 0.22) of radius
+    40 voxels centred in a 128^3 polyamide cell (E = 2.1 GPa, nu = 0.3), moduli in MPa,
+    reference medium the mean of the two stiffnesses, applied strain eps_11 = 0.05."""
+    c = n / 2.0 - 0.5
+    l = np.arange(n) - c
+    d2 = l[:, None, None] ** 2 + l[None, :, None] ** 2 + l[None, None, :] ** 2
+    ph = (d2 <= radius ** 2).astype(np.uint16)
+    C = np.stack([isotropic_voigt(2.1e3, 0.3), isotropic_voigt(72.0e3, 0.22)])
+    return Problem(f"hard_sphere{n}", (n, n, n), ph, C, 0.5 * (C[0] + C[1]),
+                   np.array([[0.05, 0, 0, 0, 0, 0]]), 1e-10, {"vf": float(ph.mean())})
+
+
 def serving_request_params(i: int, sizes=(32, 48, 64, 96, 128, 160, 192), base_seed: int = 5):
     """Grid size n, microstructure kind, contrast and load index J of request i of the
     serving stream (the draws of its generator, without building the microstructure)."""
