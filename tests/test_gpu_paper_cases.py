@@ -98,3 +98,23 @@ def test_cubic_void_comparison_operators():
     assert res["tetra"][1] < res["rotated"][1] < 100
     assert res["continuous"][0] == hz.HZ_NOT_CONVERGED and res["continuous"][2] > 1e-6
     assert res["rotated"][3] > 10 * res["tetra"][3] and res["continuous"][3] > 10 * res["tetra"][3]
+
+
+def test_iterates_versus_contrast_three_operators():
+    """Sec. 3.4's comparison as soft pins on the isolated sphere (42^3 standing in for the
+    paper's 44^3, same radius ratio): the tetrahedral counts level off as the stiff contrast
+    grows (1e3 -> 1e4 adds under half), while the continuous-frequency operator needs ten
+    times more iterates than the tetrahedral scheme from a contrast of 1e3 on."""
+    counts = {}
+    for name, green in (("tetra", hz.HZ_GREEN_TETRA), ("continuous", hz.HZ_GREEN_CONTINUOUS)):
+        for c in (1e3, 1e4):
+            p = syn.isolated_sphere(c, n=42)
+            g = hz.Grid(*p.shape)
+            g.set_material(p.C, p.phase)
+            r = g.solve(p.loads, C0=p.C0, tol=1e-10, max_iters=20000, green=green)
+            counts[name, c] = (int(r.status[0]), int(r.iters[0]))
+            _say(f"  isolated sphere C = {c:g}, {name}: status {r.status[0]}, {int(r.iters[0])} iterates")
+    assert counts["tetra", 1e3][0] == hz.HZ_OK and counts["tetra", 1e4][0] == hz.HZ_OK
+    assert counts["tetra", 1e4][1] < 1.5 * counts["tetra", 1e3][1]
+    assert counts["continuous", 1e3][1] > 10 * counts["tetra", 1e3][1]
+    assert counts["continuous", 1e4][1] > 10 * counts["tetra", 1e4][1]
