@@ -80,44 +80,37 @@ __global__ __launch_bounds__(kThreads) void k_zcon(const Desc* __restrict__ desc
       }
       const int l0 = run * m;
       const int l1 = min(l0 + m, N3);  // rows l0 .. l1-1 produced, row l1 (mod N3) read
-      cpx<double> Bn[3];
-      {
-        const int l = l1 == N3 ? 0 : l1;
-        const long long o = (long long)l * N2 + col;
-        cpx<T> s1[6], s2[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          s1[c] = gld(sp + c * zg.S + o);
-          s2[c] = gld(sp + (6 + c) * zg.S + o);
-        }
-        cpx<double> y1[3], y2[3];
-        sig_dot(s1, b1, y1);
-        sig_dot(s2, b2, y2);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Bn[c] = y1[c] + y2[c];
-      }
-#pragma unroll 1
-      for (int l = l1 - 1; l >= l0; --l) {
+      // the two tetrahedra one after the other (6 loads live at a time): T1 writes its
+      // part of R, T2 adds its own to the same elements of the same thread
+      auto half = [&](const cpx<double>(&A)[3], const cpx<double>(&B)[3], const int f, const bool add) {
+        cpx<double> Bn[3];
         {
+          const int l = l1 == N3 ? 0 : l1;
           const long long o = (long long)l * N2 + col;
-          cpx<T> s1[6], s2[6];
+          cpx<T> s[6];
 #pragma unroll
-          for (int c = 0; c < 6; ++c) {
-            s1[c] = gld(sp + c * zg.S + o);
-            s2[c] = gld(sp + (6 + c) * zg.S + o);
-          }
-          cpx<double> x1[3], x2[3], y1[3], y2[3];
-          sig_dot(s1, a1, x1);
-          sig_dot(s2, a2, x2);
-          sig_dot(s1, b1, y1);
-          sig_dot(s2, b2, y2);
+          for (int c = 0; c < 6; ++c) s[c] = gld(sp + (f + c) * zg.S + o);
+          sig_dot(s, B, Bn);
+        }
+#pragma unroll 1
+        for (int l = l1 - 1; l >= l0; --l) {
+          const long long o = (long long)l * N2 + col;
+          cpx<T> s[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) s[c] = gld(sp + (f + c) * zg.S + o);
+          cpx<double> x[3], y[3];
+          sig_dot(s, A, x);
+          sig_dot(s, B, y);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            lds.put(c * TX + col, l, fr64<T>(x1[c] + x2[c] + Bn[c]));
-            Bn[c] = y1[c] + y2[c];
+            const cpx<double> v = x[c] + Bn[c];
+            lds.put(c * TX + col, l, add ? fr64<T>(to64(lds.get(c * TX + col, l)) + v) : fr64<T>(v));
+            Bn[c] = y[c];
           }
         }
-      }
+      };
+      half(a1, b1, 0, false);
+      half(a2, b2, 6, true);
     }
   }
   __syncthreads();
