@@ -226,9 +226,9 @@ void Shape::init(int n1, int n2, int n3) {
     nbq[d] = G.H1 * (G.N2 / tx);
     // 3-field x transforms of the stencil form
     int ty3 = std::min(HZ_TY3_CAP, G.N2);
-    // FP64: row tiles small enough that 3 work-groups share a CU's 160 KB (the 3 waves per
-    // SIMD their registers allow); FP32 tiles fit 4 within the general budget
-    const int x3_lds = d ? 53 * 1024 : kLdsBytes;
+    // row tiles small enough that at least 3 work-groups share a CU's 160 KB (larger tiles
+    // left 2 at N1 = 192; tiles sized for 4 measured slower at N1 = 128 and 256)
+    const int x3_lds = 53 * 1024;
     auto x3_fits = [&](int t) { return (3 * t * hp + G.N1) * csz <= x3_lds && 3 * t * (G.N1 / 2) <= tile; };
     while (ty3 > 1 && (!x3_fits(ty3) || G.N2 % ty3)) --ty3;
     TY3[d] = x3_fits(ty3) ? ty3 : 0;
